@@ -1,0 +1,662 @@
+/*
+ * Oracle decoders: TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * Plain sequential decoders, one byte or one bit at a time, written from
+ * the format definitions.  CODAG (Section II-B) keeps the method's result
+ * identical to this sequential decode: every chunk is decoded from its
+ * first byte, in order, and only the assignment of chunks to workers
+ * changes.  Nothing here is blocked, fused or reordered.
+ *
+ * Formats (the paper names them in Section II-A and Section V-A; the bits
+ * come from the Apache ORC integer run-length encodings and RFC 1951):
+ *   - ORC integer RLE v1, signed: runs (base, delta, length) and literal
+ *     lists of zigzag base-128 varints.
+ *   - ORC integer RLE v2, signed: SHORT_REPEAT, DIRECT, PATCHED_BASE and
+ *     DELTA sub-encodings.
+ *   - Deflate (raw RFC 1951 stream per chunk): stored, fixed-Huffman and
+ *     dynamic-Huffman blocks with LZ77 back-references.
+ *
+ * Readings taken where the sources are silent (each is listed in the
+ * design notes):
+ *   - Output ends exactly at the chunk's output capacity.  RLE decodes
+ *     groups until the capacity is reached; a group that does not fit is
+ *     OVERFLOW; input that ends first is TRUNCATED; input bytes left over
+ *     after the last value are CORRUPT.
+ *   - Deflate stops at the end of the final block; fewer bytes than the
+ *     capacity is UNDERFLOW, more is OVERFLOW; bytes after the final block
+ *     are ignored.
+ *   - Within a group the fixed header fields are parsed first, then the
+ *     validity checks, then the capacity check, then the payload.
+ *   - Integer arithmetic wraps modulo 2^64.
+ *   - Varints longer than 10 bytes, or carrying bits above bit 63, are
+ *     CORRUPT.
+ *   - Huffman codes are peeked with zero bits past the end of input; a
+ *     bit pattern matching no code is CORRUPT, a matching code that runs
+ *     past the end is TRUNCATED.
+ */
+#include "oracle.h"
+
+#include <stddef.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* ORC byte reader                                                      */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    const uint8_t *buf;
+    uint64_t len;
+    uint64_t pos;
+} byte_reader;
+
+static int br_byte(byte_reader *r, uint8_t *b) {
+    if (r->pos >= r->len) return ORACLE_E_TRUNCATED;
+    *b = r->buf[r->pos++];
+    return ORACLE_OK;
+}
+
+/* Base-128 varint, least significant group first; bit 7 of a byte means
+ * "another byte follows".  At most 64 bits of value. */
+static int br_uvarint(byte_reader *r, uint64_t *v) {
+    uint64_t result = 0;
+    int i;
+    for (i = 0; i < 10; i++) {
+        uint8_t b;
+        int st = br_byte(r, &b);
+        if (st) return st;
+        if (i == 9 && b > 1) return ORACLE_E_CORRUPT; /* bits past bit 63 */
+        result |= (uint64_t)(b & 0x7f) << (7 * i);
+        if ((b & 0x80) == 0) {
+            *v = result;
+            return ORACLE_OK;
+        }
+    }
+    return ORACLE_E_CORRUPT; /* unreachable: i == 9 with b >= 0x80 returns above */
+}
+
+/* Zigzag: 0, -1, 1, -2, 2, ... are coded as 0, 1, 2, 3, 4, ... */
+static int64_t unzigzag(uint64_t z) {
+    uint64_t mag = z >> 1;
+    return (z & 1) ? (int64_t)(~mag) : (int64_t)mag;
+}
+
+static int br_svarint(byte_reader *r, int64_t *v) {
+    uint64_t z;
+    int st = br_uvarint(r, &z);
+    if (st) return st;
+    *v = unzigzag(z);
+    return ORACLE_OK;
+}
+
+/* Big-endian unsigned integer of nbytes bytes. */
+static int br_be(byte_reader *r, int nbytes, uint64_t *v) {
+    uint64_t x = 0;
+    int i;
+    for (i = 0; i < nbytes; i++) {
+        uint8_t b;
+        int st = br_byte(r, &b);
+        if (st) return st;
+        x = (x << 8) | b;
+    }
+    *v = x;
+    return ORACLE_OK;
+}
+
+static void put_i64(uint8_t *out, uint64_t index, uint64_t value) {
+    int k;
+    for (k = 0; k < 8; k++) out[index * 8 + k] = (uint8_t)(value >> (8 * k));
+}
+
+/* ------------------------------------------------------------------ */
+/* ORC integer RLE v1 (signed)                                          */
+/* ------------------------------------------------------------------ */
+/*
+ * A group starts with a signed header byte h.
+ *   h in [0, 127]:   a run of h + 3 values; a signed delta byte follows,
+ *                    then the zigzag varint base; value k is base + k*delta.
+ *   h in [-128, -1]: a literal list of -h zigzag varints.
+ * (CODAG Section II-A describes RLE v1 runs as a literal plus a length.)
+ */
+static int decode_rle_v1(const uint8_t *in, uint64_t in_len, uint8_t *out,
+                         uint64_t cap_values, uint64_t *n_out) {
+    byte_reader r = {in, in_len, 0};
+    uint64_t n = 0;
+    int st = ORACLE_OK;
+    while (n < cap_values) {
+        uint8_t hb;
+        int8_t h;
+        st = br_byte(&r, &hb);
+        if (st) goto done;
+        h = (int8_t)hb;
+        if (h >= 0) {
+            uint64_t len = (uint64_t)h + 3, k;
+            uint8_t db;
+            int64_t delta, base;
+            st = br_byte(&r, &db);
+            if (st) goto done;
+            delta = (int8_t)db;
+            st = br_svarint(&r, &base);
+            if (st) goto done;
+            if (n + len > cap_values) { st = ORACLE_E_OVERFLOW; goto done; }
+            for (k = 0; k < len; k++)
+                put_i64(out, n + k, (uint64_t)base + k * (uint64_t)delta);
+            n += len;
+        } else {
+            uint64_t len = (uint64_t)(-(int)h), k;
+            if (n + len > cap_values) { st = ORACLE_E_OVERFLOW; goto done; }
+            for (k = 0; k < len; k++) {
+                int64_t v;
+                st = br_svarint(&r, &v);
+                if (st) goto done;
+                put_i64(out, n, (uint64_t)v);
+                n++;
+            }
+        }
+    }
+    if (r.pos != r.len) st = ORACLE_E_CORRUPT; /* bytes after the last value */
+done:
+    *n_out = n;
+    return st;
+}
+
+/* ------------------------------------------------------------------ */
+/* ORC integer RLE v2 (signed)                                          */
+/* ------------------------------------------------------------------ */
+
+/* The 5-bit width code: codes 0..23 are widths 1..24; codes 24..31 are
+ * widths 26, 28, 30, 32, 40, 48, 56, 64. */
+static int orc_decode_width(int code) {
+    if (code <= 23) return code + 1;
+    switch (code) {
+    case 24: return 26;
+    case 25: return 28;
+    case 26: return 30;
+    case 27: return 32;
+    case 28: return 40;
+    case 29: return 48;
+    case 30: return 56;
+    default: return 64;
+    }
+}
+
+/* Smallest codable width that holds n bits (n >= 1); 0 if n > 64. */
+static int orc_closest_width(int n) {
+    int code;
+    for (code = 0; code < 32; code++)
+        if (orc_decode_width(code) >= n) return orc_decode_width(code);
+    return 0;
+}
+
+/*
+ * A packed section: count values of w bits each, big-endian and most
+ * significant bit first, starting at a byte boundary and padded to one.
+ */
+static int read_packed(byte_reader *r, uint64_t count, int w, uint64_t *vals) {
+    uint64_t nbytes = (count * (uint64_t)w + 7) / 8, i;
+    const uint8_t *p;
+    uint64_t bit = 0;
+    if (r->len - r->pos < nbytes) return ORACLE_E_TRUNCATED;
+    p = r->buf + r->pos;
+    for (i = 0; i < count; i++) {
+        uint64_t v = 0;
+        int j;
+        for (j = 0; j < w; j++, bit++) {
+            int b = (p[bit >> 3] >> (7 - (bit & 7))) & 1;
+            v = (v << 1) | (uint64_t)b;
+        }
+        vals[i] = v;
+    }
+    r->pos += nbytes;
+    return ORACLE_OK;
+}
+
+static int decode_rle_v2(const uint8_t *in, uint64_t in_len, uint8_t *out,
+                         uint64_t cap_values, uint64_t *n_out) {
+    byte_reader r = {in, in_len, 0};
+    uint64_t n = 0;
+    uint64_t vals[512], patches[32];
+    int st = ORACLE_OK;
+    while (n < cap_values) {
+        uint8_t b0, b1, b2, b3;
+        int type;
+        st = br_byte(&r, &b0);
+        if (st) goto done;
+        type = b0 >> 6;
+        if (type == 0) {
+            /* SHORT_REPEAT: bits 5..3 = byte width - 1, bits 2..0 = count - 3;
+             * then the zigzag value, big-endian. */
+            int w = ((b0 >> 3) & 7) + 1;
+            uint64_t len = (uint64_t)(b0 & 7) + 3, k, z;
+            if (n + len > cap_values) { st = ORACLE_E_OVERFLOW; goto done; }
+            st = br_be(&r, w, &z);
+            if (st) goto done;
+            for (k = 0; k < len; k++) put_i64(out, n + k, (uint64_t)unzigzag(z));
+            n += len;
+        } else if (type == 1) {
+            /* DIRECT: width code in bits 5..1, 9-bit (length - 1); then the
+             * zigzag values packed at that width. */
+            int w;
+            uint64_t len, k;
+            st = br_byte(&r, &b1);
+            if (st) goto done;
+            w = orc_decode_width((b0 >> 1) & 31);
+            len = ((uint64_t)(b0 & 1) << 8 | b1) + 1;
+            if (n + len > cap_values) { st = ORACLE_E_OVERFLOW; goto done; }
+            st = read_packed(&r, len, w, vals);
+            if (st) goto done;
+            for (k = 0; k < len; k++) put_i64(out, n + k, (uint64_t)unzigzag(vals[k]));
+            n += len;
+        } else if (type == 2) {
+            /* PATCHED_BASE: data width code and 9-bit (length - 1) as in
+             * DIRECT; byte 2 = (base bytes - 1) << 5 | patch width code;
+             * byte 3 = (gap bits - 1) << 5 | patch count.  Then the
+             * sign-magnitude base, the data values, and the patch list of
+             * (gap << pw | patch) entries at the closest width to gap+patch
+             * bits.  A (255, 0) entry only advances the position. */
+            int w, bw, pw, pgw, pll, ew;
+            uint64_t len, k, base_raw, cursor;
+            int64_t base;
+            st = br_byte(&r, &b1);
+            if (st) goto done;
+            st = br_byte(&r, &b2);
+            if (st) goto done;
+            st = br_byte(&r, &b3);
+            if (st) goto done;
+            w = orc_decode_width((b0 >> 1) & 31);
+            len = ((uint64_t)(b0 & 1) << 8 | b1) + 1;
+            bw = (b2 >> 5) + 1;
+            pw = orc_decode_width(b2 & 31);
+            pgw = (b3 >> 5) + 1;
+            pll = b3 & 31;
+            ew = orc_closest_width(pgw + pw);
+            if (w + pw > 64 || ew == 0) { st = ORACLE_E_CORRUPT; goto done; }
+            if (n + len > cap_values) { st = ORACLE_E_OVERFLOW; goto done; }
+            st = br_be(&r, bw, &base_raw);
+            if (st) goto done;
+            {
+                uint64_t sign = (uint64_t)1 << (8 * bw - 1);
+                if (base_raw & sign)
+                    base = -(int64_t)(base_raw & ~sign);
+                else
+                    base = (int64_t)base_raw;
+            }
+            st = read_packed(&r, len, w, vals);
+            if (st) goto done;
+            st = read_packed(&r, (uint64_t)pll, ew, patches);
+            if (st) goto done;
+            cursor = 0;
+            for (k = 0; k < (uint64_t)pll; k++) {
+                uint64_t gap = patches[k] >> pw;
+                uint64_t patch = pw == 64 ? patches[k] : (patches[k] & (((uint64_t)1 << pw) - 1));
+                cursor += gap;
+                if (gap == 255 && patch == 0) continue; /* filler entry */
+                if (cursor >= len) { st = ORACLE_E_CORRUPT; goto done; }
+                vals[cursor] |= patch << w;
+            }
+            for (k = 0; k < len; k++) put_i64(out, n + k, (uint64_t)base + vals[k]);
+            n += len;
+        } else {
+            /* DELTA: width code in bits 5..1 where code 0 means a fixed
+             * delta; 9-bit (length - 1); zigzag base varint; zigzag delta
+             * base varint; then length - 2 delta magnitudes whose sign is
+             * the delta base's. */
+            int code, w;
+            uint64_t len, k, cur;
+            int64_t base, dbase;
+            st = br_byte(&r, &b1);
+            if (st) goto done;
+            code = (b0 >> 1) & 31;
+            w = code == 0 ? 0 : orc_decode_width(code);
+            len = ((uint64_t)(b0 & 1) << 8 | b1) + 1;
+            st = br_svarint(&r, &base);
+            if (st) goto done;
+            st = br_svarint(&r, &dbase);
+            if (st) goto done;
+            if (n + len > cap_values) { st = ORACLE_E_OVERFLOW; goto done; }
+            if (w == 0) {
+                for (k = 0; k < len; k++)
+                    put_i64(out, n + k, (uint64_t)base + k * (uint64_t)dbase);
+            } else {
+                put_i64(out, n, (uint64_t)base);
+                if (len >= 2) {
+                    cur = (uint64_t)base + (uint64_t)dbase;
+                    put_i64(out, n + 1, cur);
+                    st = read_packed(&r, len - 2, w, vals);
+                    if (st) goto done;
+                    for (k = 2; k < len; k++) {
+                        if (dbase >= 0)
+                            cur += vals[k - 2];
+                        else
+                            cur -= vals[k - 2];
+                        put_i64(out, n + k, cur);
+                    }
+                }
+            }
+            n += len;
+        }
+    }
+    if (r.pos != r.len) st = ORACLE_E_CORRUPT;
+done:
+    *n_out = n;
+    return st;
+}
+
+/* ------------------------------------------------------------------ */
+/* Deflate (RFC 1951)                                                   */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    const uint8_t *buf;
+    uint64_t nbits;  /* 8 * input length */
+    uint64_t bitpos; /* next bit to consume; bits are taken LSB-first */
+} bit_reader;
+
+/* Bit i of the stream, zero past the end. */
+static int bit_at(const bit_reader *r, uint64_t i) {
+    if (i >= r->nbits) return 0;
+    return (r->buf[i >> 3] >> (i & 7)) & 1;
+}
+
+/* A value of n bits, least significant bit first. */
+static int bits(bit_reader *r, int n, uint32_t *v) {
+    uint32_t x = 0;
+    int i;
+    if (r->bitpos + (uint64_t)n > r->nbits) return ORACLE_E_TRUNCATED;
+    for (i = 0; i < n; i++) x |= (uint32_t)bit_at(r, r->bitpos + i) << i;
+    r->bitpos += n;
+    *v = x;
+    return ORACLE_OK;
+}
+
+/* Canonical Huffman code (RFC 1951 section 3.2.2): codes of equal length
+ * are consecutive and ordered by symbol; shorter codes precede longer. */
+typedef struct {
+    int count[16];   /* number of codes of each length */
+    int symbol[320]; /* symbols ordered by (length, symbol) */
+} huffman;
+
+/* Returns 0 for a complete code, > 0 for an incomplete one (the number of
+ * unused codes of length 15), < 0 if over-subscribed. */
+static int huff_build(huffman *h, const int *lengths, int n) {
+    int offs[16], len, sym, left;
+    for (len = 0; len < 16; len++) h->count[len] = 0;
+    for (sym = 0; sym < n; sym++) h->count[lengths[sym]]++;
+    left = 1;
+    for (len = 1; len < 16; len++) {
+        left <<= 1;
+        left -= h->count[len];
+        if (left < 0) return left;
+    }
+    offs[1] = 0;
+    for (len = 1; len < 15; len++) offs[len + 1] = offs[len] + h->count[len];
+    for (sym = 0; sym < n; sym++)
+        if (lengths[sym] != 0) h->symbol[offs[lengths[sym]]++] = sym;
+    return left;
+}
+
+/* Whether a set of lengths is usable: complete, or the one allowed
+ * incomplete form of exactly one code of length 1 (RFC 1951 section 3.2.7
+ * permits a single code), or (for distances only) no codes at all. */
+static int huff_usable(const huffman *h, int left, int allow_empty) {
+    int len, total = 0;
+    if (left < 0) return 0;
+    for (len = 1; len < 16; len++) total += h->count[len];
+    if (total == 0) return allow_empty;
+    if (left == 0) return 1;
+    return total == 1 && h->count[1] == 1;
+}
+
+/* Decode one symbol, reading code bits most significant first. */
+static int huff_decode(bit_reader *r, const huffman *h, int *sym) {
+    int code = 0, first = 0, index = 0, len;
+    for (len = 1; len < 16; len++) {
+        int count = h->count[len];
+        code |= bit_at(r, r->bitpos + len - 1);
+        if (code - count < first) {
+            if (r->bitpos + (uint64_t)len > r->nbits) return ORACLE_E_TRUNCATED;
+            r->bitpos += len;
+            *sym = h->symbol[index + (code - first)];
+            return ORACLE_OK;
+        }
+        index += count;
+        first += count;
+        first <<= 1;
+        code <<= 1;
+    }
+    return ORACLE_E_CORRUPT; /* matches no code */
+}
+
+/* Length symbols 257..285: base length and extra-bit count. */
+static void length_code(int sym, int *base, int *extra) {
+    int k = sym - 257;
+    if (sym == 285) { *base = 258; *extra = 0; return; }
+    if (k < 8) { *base = k + 3; *extra = 0; return; }
+    *extra = (k >> 2) - 1;
+    *base = ((4 + (k & 3)) << *extra) + 3;
+}
+
+/* Distance symbols 0..29: base distance and extra-bit count. */
+static void distance_code(int sym, int *base, int *extra) {
+    if (sym < 4) { *base = sym + 1; *extra = 0; return; }
+    *extra = (sym >> 1) - 1;
+    *base = ((2 + (sym & 1)) << *extra) + 1;
+}
+
+typedef struct {
+    uint8_t *out;
+    uint64_t cap;
+    uint64_t n;
+} out_window;
+
+static int inflate_codes(bit_reader *r, out_window *o, const huffman *lit,
+                         const huffman *dist, int have_dist) {
+    for (;;) {
+        int sym, st;
+        st = huff_decode(r, lit, &sym);
+        if (st) return st;
+        if (sym < 256) {
+            if (o->n >= o->cap) return ORACLE_E_OVERFLOW;
+            o->out[o->n++] = (uint8_t)sym;
+        } else if (sym == 256) {
+            return ORACLE_OK;
+        } else {
+            int lbase, lextra, dsym, dbase, dextra;
+            uint32_t x;
+            uint64_t len, d, k;
+            if (sym > 285) return ORACLE_E_CORRUPT;
+            length_code(sym, &lbase, &lextra);
+            st = bits(r, lextra, &x);
+            if (st) return st;
+            len = (uint64_t)lbase + x;
+            if (!have_dist) return ORACLE_E_CORRUPT;
+            st = huff_decode(r, dist, &dsym);
+            if (st) return st;
+            if (dsym > 29) return ORACLE_E_CORRUPT;
+            distance_code(dsym, &dbase, &dextra);
+            st = bits(r, dextra, &x);
+            if (st) return st;
+            d = (uint64_t)dbase + x;
+            if (d > o->n) return ORACLE_E_CORRUPT;     /* before the chunk */
+            if (o->n + len > o->cap) return ORACLE_E_OVERFLOW;
+            for (k = 0; k < len; k++) { /* byte by byte: overlap repeats */
+                o->out[o->n] = o->out[o->n - d];
+                o->n++;
+            }
+        }
+    }
+}
+
+static int inflate_stored(bit_reader *r, out_window *o) {
+    uint32_t len, nlen;
+    uint64_t k;
+    int st;
+    r->bitpos = (r->bitpos + 7) & ~(uint64_t)7; /* to a byte boundary */
+    st = bits(r, 16, &len);
+    if (st) return st;
+    st = bits(r, 16, &nlen);
+    if (st) return st;
+    if (nlen != (~len & 0xffff)) return ORACLE_E_CORRUPT;
+    if (o->n + len > o->cap) return ORACLE_E_OVERFLOW;
+    if (r->bitpos + 8 * (uint64_t)len > r->nbits) return ORACLE_E_TRUNCATED;
+    for (k = 0; k < len; k++) o->out[o->n++] = r->buf[(r->bitpos >> 3) + k];
+    r->bitpos += 8 * (uint64_t)len;
+    return ORACLE_OK;
+}
+
+static int inflate_fixed(bit_reader *r, out_window *o) {
+    int lengths[320], sym;
+    huffman lit, dist;
+    for (sym = 0; sym < 144; sym++) lengths[sym] = 8;
+    for (; sym < 256; sym++) lengths[sym] = 9;
+    for (; sym < 280; sym++) lengths[sym] = 7;
+    for (; sym < 288; sym++) lengths[sym] = 8;
+    huff_build(&lit, lengths, 288);
+    for (sym = 0; sym < 32; sym++) lengths[sym] = 5;
+    huff_build(&dist, lengths, 32);
+    return inflate_codes(r, o, &lit, &dist, 1);
+}
+
+static int inflate_dynamic(bit_reader *r, out_window *o) {
+    static const int order[19] = {16, 17, 18, 0, 8, 7, 9, 6, 10, 5,
+                                  11, 4, 12, 3, 13, 2, 14, 1, 15};
+    int lengths[320], nlen, ndist, ncode, index, left, st;
+    uint32_t x;
+    huffman lencode, lit, dist;
+
+    st = bits(r, 5, &x);
+    if (st) return st;
+    nlen = (int)x + 257;
+    st = bits(r, 5, &x);
+    if (st) return st;
+    ndist = (int)x + 1;
+    st = bits(r, 4, &x);
+    if (st) return st;
+    ncode = (int)x + 4;
+    if (nlen > 286 || ndist > 30) return ORACLE_E_CORRUPT;
+
+    for (index = 0; index < 19; index++) lengths[index] = 0;
+    for (index = 0; index < ncode; index++) {
+        st = bits(r, 3, &x);
+        if (st) return st;
+        lengths[order[index]] = (int)x;
+    }
+    left = huff_build(&lencode, lengths, 19);
+    if (left != 0) return ORACLE_E_CORRUPT; /* code-length code must be complete */
+
+    index = 0;
+    while (index < nlen + ndist) {
+        int sym, len = 0, rep;
+        st = huff_decode(r, &lencode, &sym);
+        if (st) return st;
+        if (sym < 16) {
+            lengths[index++] = sym;
+            continue;
+        }
+        if (sym == 16) {
+            if (index == 0) return ORACLE_E_CORRUPT;
+            len = lengths[index - 1];
+            st = bits(r, 2, &x);
+            if (st) return st;
+            rep = 3 + (int)x;
+        } else if (sym == 17) {
+            st = bits(r, 3, &x);
+            if (st) return st;
+            rep = 3 + (int)x;
+        } else {
+            st = bits(r, 7, &x);
+            if (st) return st;
+            rep = 11 + (int)x;
+        }
+        if (index + rep > nlen + ndist) return ORACLE_E_CORRUPT;
+        while (rep--) lengths[index++] = len;
+    }
+    if (lengths[256] == 0) return ORACLE_E_CORRUPT; /* no end-of-block code */
+
+    left = huff_build(&lit, lengths, nlen);
+    if (!huff_usable(&lit, left, 0)) return ORACLE_E_CORRUPT;
+    left = huff_build(&dist, lengths + nlen, ndist);
+    if (!huff_usable(&dist, left, 1)) return ORACLE_E_CORRUPT;
+    {
+        int any = 0, len;
+        for (len = 1; len < 16; len++) any |= dist.count[len];
+        return inflate_codes(r, o, &lit, &dist, any != 0);
+    }
+}
+
+static int decode_deflate(const uint8_t *in, uint64_t in_len, uint8_t *out,
+                          uint64_t cap, uint64_t *n_out) {
+    bit_reader r = {in, 8 * in_len, 0};
+    out_window o = {out, cap, 0};
+    int st = ORACLE_OK;
+    for (;;) {
+        uint32_t last, type;
+        st = bits(&r, 1, &last);
+        if (st) break;
+        st = bits(&r, 2, &type);
+        if (st) break;
+        if (type == 0)
+            st = inflate_stored(&r, &o);
+        else if (type == 1)
+            st = inflate_fixed(&r, &o);
+        else if (type == 2)
+            st = inflate_dynamic(&r, &o);
+        else
+            st = ORACLE_E_CORRUPT;
+        if (st) break;
+        if (last) {
+            if (o.n != o.cap) st = ORACLE_E_UNDERFLOW;
+            break;
+        }
+    }
+    *n_out = o.n;
+    return st;
+}
+
+/* ------------------------------------------------------------------ */
+/* Entry points                                                         */
+/* ------------------------------------------------------------------ */
+
+int oracle_decode_chunk(int codec, const uint8_t *in, uint64_t in_len,
+                        uint8_t *out, uint64_t out_cap, uint64_t *produced) {
+    uint64_t n = 0;
+    int st;
+    *produced = 0;
+    if (codec == ORACLE_RLE_V1 || codec == ORACLE_RLE_V2) {
+        /* Values are whole little-endian int64s starting 8-byte aligned. */
+        if (out_cap % 8 != 0 || ((uintptr_t)out & 7) != 0) return ORACLE_E_INVALID_ARGUMENT;
+        if (codec == ORACLE_RLE_V1)
+            st = decode_rle_v1(in, in_len, out, out_cap / 8, &n);
+        else
+            st = decode_rle_v2(in, in_len, out, out_cap / 8, &n);
+        *produced = n * 8;
+        return st;
+    }
+    if (codec == ORACLE_DEFLATE) {
+        st = decode_deflate(in, in_len, out, out_cap, &n);
+        *produced = n;
+        return st;
+    }
+    return ORACLE_E_INVALID_ARGUMENT;
+}
+
+int oracle_decompress(int codec, const uint8_t *comp,
+                      const uint64_t *chunk_offsets, uint8_t *out,
+                      const uint64_t *out_offsets, uint64_t n_chunks,
+                      int32_t *status) {
+    uint64_t i;
+    if (codec < ORACLE_RLE_V1 || codec > ORACLE_DEFLATE) return -1;
+    if (n_chunks && (!comp || !chunk_offsets || !out || !out_offsets)) return -1;
+    for (i = 0; i < n_chunks; i++) {
+        uint64_t produced;
+        int st;
+        if (chunk_offsets[i + 1] < chunk_offsets[i] || out_offsets[i + 1] < out_offsets[i])
+            st = ORACLE_E_INVALID_ARGUMENT;
+        else
+            st = oracle_decode_chunk(codec, comp + chunk_offsets[i],
+                                     chunk_offsets[i + 1] - chunk_offsets[i],
+                                     out + out_offsets[i],
+                                     out_offsets[i + 1] - out_offsets[i], &produced);
+        if (status) status[i] = st;
+    }
+    return 0;
+}

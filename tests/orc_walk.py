@@ -1,0 +1,91 @@
+"""Minimal ORC file walker (test helper).
+
+Extracts the raw DATA stream of an integer column from an uncompressed ORC
+file written by pyarrow (Apache ORC's C++ writer), so the oracle's RLE
+decoders can be checked against an independent implementation.  Only the
+protobuf fields needed to find the stream are read: postscript -> footer ->
+stripe information -> stripe footer -> stream list.
+"""
+from __future__ import annotations
+
+
+def _varint(buf: bytes, i: int):
+    shift = result = 0
+    while True:
+        b = buf[i]
+        i += 1
+        result |= (b & 0x7F) << shift
+        if b < 0x80:
+            return result, i
+        shift += 7
+
+
+def _fields(buf: bytes):
+    """Yield (field number, wire type, value) of a protobuf message."""
+    i = 0
+    while i < len(buf):
+        key, i = _varint(buf, i)
+        num, wt = key >> 3, key & 7
+        if wt == 0:
+            v, i = _varint(buf, i)
+        elif wt == 1:
+            v, i = buf[i:i + 8], i + 8
+        elif wt == 2:
+            n, i = _varint(buf, i)
+            v, i = buf[i:i + n], i + n
+        elif wt == 5:
+            v, i = buf[i:i + 4], i + 4
+        else:
+            raise ValueError(f"unsupported wire type {wt}")
+        yield num, wt, v
+
+
+def integer_data_streams(path: str, column: int = 1):
+    """Return (encoding kind, [DATA stream bytes per stripe]) for a column.
+
+    Encoding kind is ORC's ColumnEncoding kind: 0 = DIRECT (RLE v1),
+    2 = DIRECT_V2 (RLE v2).
+    """
+    data = open(path, "rb").read()
+    ps_len = data[-1]
+    ps = data[-1 - ps_len:-1]
+    footer_len = compression = None
+    for num, _, v in _fields(ps):
+        if num == 1:
+            footer_len = v
+        elif num == 2:
+            compression = v
+    if compression not in (None, 0):
+        raise ValueError("only uncompressed ORC files are supported")
+    footer = data[-1 - ps_len - footer_len:-1 - ps_len]
+    stripes = []
+    for num, _, v in _fields(footer):
+        if num == 3:
+            info = {n: val for n, _, val in _fields(v)}
+            stripes.append(info)
+    out, kinds = [], set()
+    for st in stripes:
+        offset, index_len, data_len, sf_len = st[1], st.get(2, 0), st[3], st[4]
+        sf = data[offset + index_len + data_len: offset + index_len + data_len + sf_len]
+        streams, encodings = [], []
+        for num, _, v in _fields(sf):
+            if num == 1:
+                streams.append({n: val for n, _, val in _fields(v)})
+            elif num == 2:
+                encodings.append({n: val for n, _, val in _fields(v)})
+        pos = offset
+        found = None
+        for s in streams:
+            kind, col, length = s.get(1, 0), s.get(2, 0), s.get(3, 0)
+            if col == column and kind == 0:
+                raise ValueError("column has a PRESENT stream (nulls); not supported")
+            if col == column and kind == 1:
+                found = data[pos:pos + length]
+            pos += length
+        if found is None:
+            raise ValueError("no DATA stream for the column")
+        kinds.add(encodings[column].get(1, 0))
+        out.append(found)
+    if len(kinds) != 1:
+        raise ValueError("mixed encodings across stripes")
+    return kinds.pop(), out
