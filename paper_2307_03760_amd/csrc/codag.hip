@@ -1,0 +1,224 @@
+// Kernels and the C ABI of the chunk-parallel decompressor.
+//
+// One 64-lane wavefront decodes one chunk (CODAG Section IV-C: the warp is
+// the decompression unit); a workgroup holds `waves_per_block` independent
+// waves that never synchronize with each other, so workgroups are only a
+// dispatch and LDS-allocation unit.  Chunk i of the plain launch is handled
+// by wave (blockIdx.x * waves_per_block + wave) and the hardware dispatcher
+// balances uneven chunks by handing out workgroups as slots free up.
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+
+#include "../../include/codag.h"
+#include "deflate.hpp"
+#include "rle.hpp"
+
+namespace codag {
+
+constexpr uint32_t kRleV1Lds = kRingLdsBytes + 128 * 4;  // ring + literal-list terminator slots
+constexpr uint32_t kRleV2Lds = kRingLdsBytes;
+
+template <int TB>
+constexpr uint32_t deflate_lds_bytes() {
+    return (uint32_t)((sizeof(DeflateLds<TB>) + 15) & ~size_t(15));
+}
+
+__device__ __forceinline__ uint64_t error_key(uint64_t chunk, int st) {
+    return (chunk << 4) | (uint64_t)(uint32_t)(-st);
+}
+
+// Decodes chunk c with the calling wave; returns its status.  `lds` is this
+// wave's LDS slice.
+template <int Codec, int TB>
+__device__ __forceinline__ int decode_one(const uint8_t *comp, const uint64_t *coff, uint8_t *out,
+                                          const uint64_t *ooff, uint64_t c, uint8_t *lds) {
+    uint64_t i0 = coff[c], i1 = coff[c + 1], o0 = ooff[c], o1 = ooff[c + 1];
+    if (i1 < i0 || o1 < o0 || i1 - i0 >= (1ull << 31) || o1 - o0 >= (1ull << 31))
+        return CODAG_E_INVALID_ARGUMENT;
+    uint32_t in_len = (uint32_t)(i1 - i0), out_len = (uint32_t)(o1 - o0);
+    uint8_t *dst = out + o0;
+    InRing in;
+    if constexpr (Codec == CODAG_DEFLATE) {
+        auto *d = reinterpret_cast<DeflateLds<TB> *>(lds);
+        in.init(comp + i0, in_len, d->ring);
+        return decode_deflate<TB>(in, dst, out_len, d);
+    } else {
+        if ((out_len & 7) || (reinterpret_cast<uintptr_t>(dst) & 7)) return CODAG_E_INVALID_ARGUMENT;
+        in.init(comp + i0, in_len, reinterpret_cast<uint32_t *>(lds));
+        uint64_t *dst64 = reinterpret_cast<uint64_t *>(dst);
+        if constexpr (Codec == CODAG_RLE_V1)
+            return decode_rle_v1(in, dst64, out_len / 8,
+                                 reinterpret_cast<uint32_t *>(lds + kRingLdsBytes));
+        else
+            return decode_rle_v2(in, dst64, out_len / 8);
+    }
+}
+
+__device__ __forceinline__ void report(uint64_t c, int st, int32_t *status,
+                                       unsigned long long *err) {
+    if (lane() == 0) {
+        if (status) status[c] = st;
+        if (st != CODAG_OK) atomicMin(err, (unsigned long long)error_key(c, st));
+    }
+}
+
+// Plain launch: one chunk per wave, every chunk of one codec.
+template <int Codec, int TB>
+__global__ void __launch_bounds__(1024) decode_plain(const uint8_t *comp, const uint64_t *coff,
+                                                     uint8_t *out, const uint64_t *ooff, uint64_t n,
+                                                     uint32_t lds_per_wave, int32_t *status,
+                                                     unsigned long long *err, uint64_t *ticks) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint32_t wave = uni(threadIdx.x / kWave);
+    uint32_t wpb = blockDim.x / kWave;
+    uint64_t c = (uint64_t)blockIdx.x * wpb + wave;
+    if (c >= n) return;
+    uint64_t t0 = ticks ? __builtin_amdgcn_s_memtime() : 0;
+    int st = decode_one<Codec, TB>(comp, coff, out, ooff, c, smem + wave * lds_per_wave);
+    if (ticks && lane() == 0) ticks[c] = __builtin_amdgcn_s_memtime() - t0;
+    report(c, st, status, err);
+}
+
+}  // namespace codag
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+namespace {
+
+using namespace codag;
+
+constexpr int kMaxDevices = 64;
+
+struct DeviceState {
+    unsigned long long *err = nullptr;  // first-error word: (chunk << 4) | -status
+};
+
+std::mutex g_mu;
+DeviceState g_dev[kMaxDevices];
+
+int device_state(DeviceState **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return CODAG_E_HIP;
+    std::lock_guard<std::mutex> lock(g_mu);
+    DeviceState &s = g_dev[dev];
+    if (!s.err) {
+        unsigned long long *p = nullptr;
+        if (hipMalloc(&p, sizeof(*p)) != hipSuccess) return CODAG_E_HIP;
+        unsigned long long none = ~0ull;
+        if (hipMemcpy(p, &none, sizeof(none), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(p);
+            return CODAG_E_HIP;
+        }
+        s.err = p;
+    }
+    *out = &s;
+    return CODAG_OK;
+}
+
+template <int Codec, int TB>
+int launch_plain(const uint8_t *comp, const uint64_t *coff, uint8_t *out, const uint64_t *ooff,
+                 uint64_t n, int wpb, int32_t *status, unsigned long long *err, uint64_t *ticks,
+                 hipStream_t stream) {
+    uint32_t per_wave = Codec == CODAG_DEFLATE ? deflate_lds_bytes<TB>()
+                        : Codec == CODAG_RLE_V1 ? kRleV1Lds
+                                                : kRleV2Lds;
+    size_t shmem = (size_t)per_wave * wpb;
+    auto kern = decode_plain<Codec, TB>;
+    static std::once_flag once;
+    std::call_once(once, [&] {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    });
+    uint64_t grid = (n + wpb - 1) / wpb;
+    hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(kWave * wpb), shmem, stream, comp, coff,
+                       out, ooff, n, per_wave, status, err, ticks);
+    return hipGetLastError() == hipSuccess ? CODAG_OK : CODAG_E_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int codag_decompress_ex(int codec, const uint8_t *comp_buf, const uint64_t *chunk_offsets,
+                        uint8_t *out_buf, const uint64_t *out_offsets, uint64_t n_chunks,
+                        void *stream, int32_t *chunk_status, const codag_opts *opts) {
+    if (codec != CODAG_RLE_V1 && codec != CODAG_RLE_V2 && codec != CODAG_DEFLATE)
+        return CODAG_E_INVALID_ARGUMENT;
+    if (n_chunks == 0) return CODAG_OK;
+    if (!comp_buf || !chunk_offsets || !out_buf || !out_offsets) return CODAG_E_INVALID_ARGUMENT;
+    if (n_chunks > (1ull << 40)) return CODAG_E_INVALID_ARGUMENT;
+    int wpb = opts && opts->waves_per_block ? opts->waves_per_block : 4;
+    int tb = opts && opts->lit_table_bits ? opts->lit_table_bits : 10;
+    if (wpb < 1 || wpb > 16 || tb < 9 || tb > 11) return CODAG_E_INVALID_ARGUMENT;
+    uint64_t *ticks = opts ? opts->chunk_ticks : nullptr;
+    DeviceState *ds = nullptr;
+    int st = device_state(&ds);
+    if (st) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    switch (codec) {
+        case CODAG_RLE_V1:
+            return launch_plain<CODAG_RLE_V1, 10>(comp_buf, chunk_offsets, out_buf, out_offsets,
+                                                  n_chunks, wpb, chunk_status, ds->err, ticks, s);
+        case CODAG_RLE_V2:
+            return launch_plain<CODAG_RLE_V2, 10>(comp_buf, chunk_offsets, out_buf, out_offsets,
+                                                  n_chunks, wpb, chunk_status, ds->err, ticks, s);
+        default:
+            if (tb == 9)
+                return launch_plain<CODAG_DEFLATE, 9>(comp_buf, chunk_offsets, out_buf, out_offsets,
+                                                      n_chunks, wpb, chunk_status, ds->err, ticks, s);
+            if (tb == 11)
+                return launch_plain<CODAG_DEFLATE, 11>(comp_buf, chunk_offsets, out_buf, out_offsets,
+                                                       n_chunks, wpb, chunk_status, ds->err, ticks, s);
+            return launch_plain<CODAG_DEFLATE, 10>(comp_buf, chunk_offsets, out_buf, out_offsets,
+                                                   n_chunks, wpb, chunk_status, ds->err, ticks, s);
+    }
+}
+
+int codag_decompress(int codec, const uint8_t *comp_buf, const uint64_t *chunk_offsets,
+                     uint8_t *out_buf, const uint64_t *out_offsets, uint64_t n_chunks,
+                     void *stream) {
+    return codag_decompress_ex(codec, comp_buf, chunk_offsets, out_buf, out_offsets, n_chunks,
+                               stream, nullptr, nullptr);
+}
+
+int codag_get_error(void *stream, uint64_t *first_bad_chunk) {
+    if (first_bad_chunk) *first_bad_chunk = UINT64_MAX;
+    DeviceState *ds = nullptr;
+    int st = device_state(&ds);
+    if (st) return st;
+    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return CODAG_E_HIP;
+    unsigned long long key = 0, none = ~0ull;
+    if (hipMemcpy(&key, ds->err, sizeof(key), hipMemcpyDeviceToHost) != hipSuccess) return CODAG_E_HIP;
+    if (key == none) return CODAG_OK;
+    if (hipMemcpy(ds->err, &none, sizeof(none), hipMemcpyHostToDevice) != hipSuccess) return CODAG_E_HIP;
+    if (first_bad_chunk) *first_bad_chunk = key >> 4;
+    return -(int)(key & 15);
+}
+
+const char *codag_status_string(int status) {
+    switch (status) {
+        case CODAG_OK: return "ok";
+        case CODAG_E_INVALID_ARGUMENT: return "invalid argument";
+        case CODAG_E_HIP: return "HIP runtime error";
+        case CODAG_E_CORRUPT: return "corrupt stream";
+        case CODAG_E_TRUNCATED: return "truncated stream";
+        case CODAG_E_OVERFLOW: return "output range too small";
+        case CODAG_E_UNDERFLOW: return "output range too large";
+        default: return "unknown status";
+    }
+}
+
+void codag_shutdown(void) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    for (auto &s : g_dev) {
+        if (s.err) {
+            (void)hipFree(s.err);
+            s.err = nullptr;
+        }
+    }
+}
+
+}  // extern "C"

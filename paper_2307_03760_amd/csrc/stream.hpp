@@ -1,0 +1,137 @@
+// input_stream / output_stream for one wavefront (CODAG Section IV-B, IV-E,
+// IV-F).
+//
+// Input (the "conditional A" refill of Section IV-A): the chunk's compressed
+// bytes reach the wave through a 2 KiB ring in LDS, filled 1 KiB at a time
+// by one coalesced 16-byte load per lane.  The next 1 KiB is always in
+// flight in registers while the current one is consumed, so the load latency
+// overlaps decoding.  Bytes past the end of the chunk read as zero.  Readers
+// see 32-bit words; the ring carries a copy of its first 16 bytes after its
+// end so any run of four consecutive words is contiguous.
+//
+// Positions are byte offsets from `gbase`, the chunk start rounded down to 16
+// bytes, and fit in 32 bits (chunks are below 2 GiB).
+#pragma once
+
+#include "wave.hpp"
+
+namespace codag {
+
+constexpr uint32_t kRingBytes = 2048;
+constexpr uint32_t kRingWords = kRingBytes / 4;
+constexpr uint32_t kRingLdsBytes = kRingBytes + 16;  // + mirror of the first 16 bytes
+constexpr uint32_t kFetchBytes = 1024;                // 64 lanes x 16 bytes
+
+struct InRing {
+    const uint8_t *gbase;  // 16-byte aligned
+    uint32_t skip;         // chunk start relative to gbase (0..15)
+    uint32_t gend;         // one past the chunk's last byte, relative to gbase
+    uint32_t loaded;       // bytes [loaded - 2048, loaded) are in the ring
+    uint32_t *ring;        // this wave's LDS ring (kRingLdsBytes)
+    uint4 pend;            // this lane's 16 bytes of [loaded, loaded + 1024), in flight
+
+    __device__ __forceinline__ void issue() {
+        uint32_t at = loaded + 16 * lane();
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (at < gend) v = *reinterpret_cast<const uint4 *>(gbase + at);
+        pend = v;
+    }
+
+    __device__ __forceinline__ void init(const uint8_t *chunk, uint32_t len, uint32_t *lds) {
+        uintptr_t a = reinterpret_cast<uintptr_t>(chunk);
+        gbase = reinterpret_cast<const uint8_t *>(a & ~(uintptr_t)15);
+        skip = (uint32_t)(a & 15);
+        gend = skip + len;
+        loaded = 0;
+        ring = lds;
+        issue();
+    }
+
+    // Move the in-flight kilobyte into the ring and start loading the next.
+    __device__ __forceinline__ void commit() {
+        uint32_t at = loaded + 16 * lane();
+        uint4 v = pend;
+        if (at + 16 > gend) {  // zero the bytes past the end of the chunk
+            uint32_t valid = at < gend ? gend - at : 0;
+            uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                int keep = (int)valid - 4 * k;
+                uint32_t m = keep >= 4 ? 0xffffffffu : keep <= 0 ? 0u : ((1u << (8 * keep)) - 1);
+                w[k] &= m;
+            }
+            v = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        uint32_t half = (loaded / kFetchBytes) & 1;
+        reinterpret_cast<uint4 *>(ring)[half * 64 + lane()] = v;
+        if (half == 0 && lane() == 0) reinterpret_cast<uint4 *>(ring)[128] = v;
+        loaded += kFetchBytes;
+        issue();
+    }
+
+    // Make bytes [end - 1024, end) readable.
+    __device__ __forceinline__ void ensure(uint32_t end) {
+        while (loaded < end) commit();
+    }
+
+    // Restart the ring at byte position pos (after a long jump ahead).
+    __device__ __forceinline__ void restart(uint32_t pos) {
+        loaded = pos & ~(kFetchBytes - 1);
+        issue();
+    }
+
+    __device__ __forceinline__ uint32_t word(uint32_t w) const { return ring[w & (kRingWords - 1)]; }
+    // Words w and w+1 (w+1 may be the mirror).
+    __device__ __forceinline__ uint32_t word_next(uint32_t w) const {
+        return ring[(w & (kRingWords - 1)) + 1];
+    }
+    __device__ __forceinline__ uint32_t word_at(uint32_t w, uint32_t k) const {
+        return ring[(w & (kRingWords - 1)) + k];
+    }
+
+    // Eight bytes starting at byte position pos, little-endian, identical on
+    // all lanes (needs ensure(pos + 12)).
+    __device__ __forceinline__ uint64_t peek8(uint32_t pos) const {
+        uint32_t w = pos >> 2;
+        uint32_t a = word_at(w, 0), b = word_at(w, 1), c = word_at(w, 2);
+        uint32_t sh = 8 * (pos & 3);
+        uint64_t lo = ((uint64_t)b << 32) | a;
+        uint64_t r = sh ? (lo >> sh) | ((uint64_t)c << (64 - sh)) : lo;
+        return uni64(r);
+    }
+};
+
+// Sixteen bytes at position pos as little-endian (lo, hi) pairs, per lane
+// (needs the four words from pos >> 2 readable).
+__device__ __forceinline__ void ring_read16(const InRing &in, uint32_t pos, uint64_t &lo, uint64_t &hi) {
+    uint32_t w = pos >> 2;
+    uint32_t a = in.word_at(w, 0), b = in.word_at(w, 1), c = in.word_at(w, 2), d = in.word_at(w, 3);
+    uint32_t sh = 8 * (pos & 3);
+    uint64_t x0 = ((uint64_t)b << 32) | a, x1 = ((uint64_t)d << 32) | c;
+    if (sh) {
+        lo = (x0 >> sh) | (x1 << (64 - sh));
+        hi = x1 >> sh;
+    } else {
+        lo = x0;
+        hi = x1;
+    }
+}
+
+// W bits (1..64) most significant first, starting `bit` bits into the byte
+// stream at byte position 0 of the ring's coordinates (per lane).
+__device__ __forceinline__ uint64_t ring_bits_msb(const InRing &in, uint64_t bit, uint32_t w) {
+    uint32_t byte = (uint32_t)(bit >> 3);
+    uint32_t wi = byte >> 2;
+    uint32_t o = 8 * (byte & 3) + (uint32_t)(bit & 7);  // 0..31
+    uint64_t hi = ((uint64_t)bswap32(in.word_at(wi, 0)) << 32) | bswap32(in.word_at(wi, 1));
+    uint32_t lo = bswap32(in.word_at(wi, 2));
+    uint64_t top = o ? (hi << o) | ((uint64_t)lo >> (32 - o)) : hi;
+    return w >= 64 ? top : top >> (64 - w);
+}
+
+// Stores a little-endian value of `n` (1..4) bytes at an arbitrary address.
+__device__ __forceinline__ void store_bytes(uint8_t *p, uint32_t v, uint32_t n) {
+    for (uint32_t k = 0; k < n; k++) p[k] = (uint8_t)(v >> (8 * k));
+}
+
+}  // namespace codag

@@ -1,0 +1,241 @@
+"""GPU parity: the HIP path, called through the C ABI, against the oracle.
+
+Bit-exact output and equal per-chunk status on the same seeded inputs, at
+small sizes spanning several chunks with a ragged tail, at the full workload
+sizes in the benchmark's launch configuration, and on edge and corrupt cases.
+"""
+import sys
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from workloads import enc
+
+from gpu_util import assert_parity, gpu_decode
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2307_03760_amd as codag
+    codag.lib()
+    return torch.device("cuda:0")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _chunks(codec, blobs, sizes):
+    return workloads._pack([codec] * len(blobs), blobs, sizes)
+
+
+# ---- small workloads: several chunks and a ragged tail ---------------------
+
+@pytest.mark.parametrize("wpb", [1, 4, 7])
+def test_rle_v1_small(dev, wpb):
+    ch = workloads.rle_v1_workload(seed=5, n_values=100_003, chunk_values=16384)
+    _say(f"rle_v1 small wpb={wpb} chunks={ch.n_chunks}")
+    assert (assert_parity(oracle.RLE_V1, ch, dev, waves_per_block=wpb) == 0).all()
+
+
+@pytest.mark.parametrize("wpb", [1, 4, 7])
+def test_rle_v2_small(dev, wpb):
+    ch = workloads.rle_v2_workload(seed=5, n_values=300_001, chunk_values=32768)
+    _say(f"rle_v2 small wpb={wpb} chunks={ch.n_chunks}")
+    assert (assert_parity(oracle.RLE_V2, ch, dev, waves_per_block=wpb) == 0).all()
+
+
+@pytest.mark.parametrize("tb", [9, 10, 11])
+def test_deflate_small(dev, tb):
+    ch = workloads.deflate_workload(seed=5, total_bytes=48 * 65536)
+    _say(f"deflate small tb={tb} chunks={ch.n_chunks}")
+    assert (assert_parity(oracle.DEFLATE, ch, dev, lit_table_bits=tb) == 0).all()
+
+
+def test_rle_v2_each_subencoding(dev):
+    rng = np.random.default_rng(21)
+    blobs, sizes = [], []
+    for kind in (enc.SHORT_REPEAT, enc.DIRECT, enc.PATCHED_BASE, enc.DELTA, enc.AUTO):
+        for trial in range(12):
+            n = int(rng.integers(1, 3000))
+            bits = int(rng.integers(1, 64))
+            if kind == enc.SHORT_REPEAT:
+                v = np.repeat(rng.integers(-(1 << 62), 1 << 62, n), rng.integers(1, 12, n))[:n]
+            elif kind == enc.DELTA:
+                v = np.cumsum(rng.integers(0, 1 << min(bits, 40), n)) * (1 if trial % 2 else -1)
+            elif kind == enc.PATCHED_BASE:
+                v = np.where(rng.random(n) < 0.04, rng.integers(0, 1 << 50, n), rng.integers(0, 1 << 11, n))
+                if trial % 3 == 0:
+                    v = np.where(np.arange(n) % 611 == 7, 1 << 47, rng.integers(0, 4000, n))
+            else:
+                v = rng.integers(-(1 << (bits - 1)), 1 << (bits - 1), n)
+            v = np.asarray(v, dtype=np.int64)
+            blobs.append(enc.encode_rle_v2(v, np.array([n]), np.array([kind], dtype=np.uint8)))
+            sizes.append(8 * n)
+    ch = _chunks(oracle.RLE_V2, blobs, sizes)
+    _say(f"rle_v2 forced sub-encodings chunks={ch.n_chunks}")
+    assert (assert_parity(oracle.RLE_V2, ch, dev) == 0).all()
+
+
+def test_rle_extremes(dev):
+    I64_MIN, I64_MAX = -(1 << 63), (1 << 63) - 1
+    vals = [np.array([I64_MIN, I64_MAX, 0, -1, 1] * 40, dtype=np.int64),
+            np.arange(1000, dtype=np.int64) * -128,
+            (np.uint64(I64_MAX - 200) + np.arange(500, dtype=np.uint64)).view(np.int64),
+            np.random.default_rng(3).integers(I64_MIN, I64_MAX, 777, dtype=np.int64)]
+    for codec, encode in ((oracle.RLE_V1, enc.encode_rle_v1), (oracle.RLE_V2, enc.encode_rle_v2)):
+        ch = _chunks(codec, [encode(v) for v in vals], [8 * v.size for v in vals])
+        _say(f"rle extremes codec={codec}")
+        assert (assert_parity(codec, ch, dev) == 0).all()
+
+
+def test_deflate_strategies_and_levels(dev):
+    rng = np.random.default_rng(8)
+    vocab = workloads._vocab(0)
+    datas = [b"", b"x", bytes(70000), bytes(range(7)) * 9000, workloads.zipf_text(90000, rng, vocab),
+             workloads.int32_column(65536, rng), workloads.random_bytes(100000, rng),
+             workloads.int32_column(65536, rng, run_heavy=True)]
+    blobs, sizes = [], []
+    for d in datas:
+        for level in (0, 1, 6, 9):
+            for strategy in (zlib.Z_DEFAULT_STRATEGY, zlib.Z_HUFFMAN_ONLY, zlib.Z_RLE, zlib.Z_FIXED):
+                co = zlib.compressobj(level, zlib.DEFLATED, -15, 8, strategy)
+                blobs.append(co.compress(d) + co.flush())
+                sizes.append(len(d))
+    ch = _chunks(oracle.DEFLATE, blobs, sizes)
+    _say(f"deflate strategies chunks={ch.n_chunks}")
+    assert (assert_parity(oracle.DEFLATE, ch, dev) == 0).all()
+
+
+def test_unaligned_chunk_layout(dev):
+    """Compressed chunks at odd offsets, Deflate outputs at odd offsets."""
+    rng = np.random.default_rng(4)
+    blobs, sizes = [], []
+    for i in range(40):
+        d = workloads.zipf_text(int(rng.integers(1, 30000)), rng, workloads._vocab(0))
+        blobs.append(workloads.deflate_raw(d, fixed=bool(i % 3 == 0)))
+        sizes.append(len(d))
+    ch = _chunks(oracle.DEFLATE, blobs, sizes)
+    assert (assert_parity(oracle.DEFLATE, ch, dev) == 0).all()
+
+
+# ---- edge cases -------------------------------------------------------------
+
+def test_empty_and_degenerate(dev):
+    import paper_2307_03760_amd as codag
+    # zero chunks is a no-op
+    ch = _chunks(oracle.RLE_V1, [], [])
+    out, st = gpu_decode(oracle.RLE_V1, ch, dev)
+    assert st.size == 0
+    # empty chunks: OK when both sides are empty, CORRUPT for leftover input,
+    # TRUNCATED when output is expected from no input
+    for codec, one in ((oracle.RLE_V1, enc.encode_rle_v1(np.array([5], dtype=np.int64))),
+                       (oracle.RLE_V2, enc.encode_rle_v2(np.array([5], dtype=np.int64)))):
+        ch = _chunks(codec, [b"", one, b"", one], [0, 0, 8, 8])
+        st = assert_parity(codec, ch, dev)
+        assert st.tolist() == [0, oracle.E_CORRUPT, oracle.E_TRUNCATED, 0]
+    ch = _chunks(oracle.DEFLATE, [b"", b"\x03\x00", b"\x03\x00", b"\x01\x00\x00\xff\xff"], [0, 0, 5, 0])
+    st = assert_parity(oracle.DEFLATE, ch, dev)
+    assert st.tolist() == [oracle.E_TRUNCATED, 0, oracle.E_UNDERFLOW, 0]
+    codag.get_error()
+
+
+def test_rle_output_rules(dev):
+    import torch
+    import paper_2307_03760_amd as codag
+    one = enc.encode_rle_v1(np.arange(4, dtype=np.int64))
+    ch = _chunks(oracle.RLE_V1, [one, one], [32, 32])
+    comp, co, oo = [torch.from_numpy(np.ascontiguousarray(a).view(np.uint8 if a.dtype == np.uint8 else np.int64)).to(dev)
+                    for a in (ch.comp, ch.chunk_offsets, ch.out_offsets)]
+    out = torch.zeros(80, dtype=torch.uint8, device=dev)
+    st = torch.zeros(2, dtype=torch.int32, device=dev)
+    # shift the output by 4 bytes: both chunks misaligned
+    codag.decompress(oracle.RLE_V1, comp, co, out[4:68], oo, status=st)
+    assert st.cpu().tolist() == [oracle.E_INVALID_ARGUMENT] * 2
+    assert (out.cpu().numpy() == 0).all()  # nothing written
+    rc, bad = codag.get_error()
+    assert rc == oracle.E_INVALID_ARGUMENT and bad == 0
+    assert codag.get_error() == (0, None)  # cleared
+
+
+def test_capacity_statuses(dev):
+    vals = np.arange(200, dtype=np.int64) * 7
+    blobs, sizes = [], []
+    for codec, encode in ((oracle.RLE_V1, enc.encode_rle_v1), (oracle.RLE_V2, enc.encode_rle_v2)):
+        data = encode(vals)
+        ch = _chunks(codec, [data, data, data, data + b"\x00", data[:-1]], [1600, 1592, 1608, 1600, 1600])
+        st = assert_parity(codec, ch, dev)
+        assert st.tolist() == [0, oracle.E_OVERFLOW, oracle.E_TRUNCATED, oracle.E_CORRUPT, oracle.E_TRUNCATED]
+    d = workloads.zipf_text(30000, np.random.default_rng(2), workloads._vocab(0))
+    z = workloads.deflate_raw(d)
+    ch = _chunks(oracle.DEFLATE, [z, z, z, z[:-3], z + b"junk"], [len(d), len(d) - 1, len(d) + 1, len(d), len(d)])
+    st = assert_parity(oracle.DEFLATE, ch, dev)
+    assert st.tolist() == [0, oracle.E_OVERFLOW, oracle.E_UNDERFLOW, oracle.E_TRUNCATED, 0]
+
+
+# ---- corrupt inputs: same status class as the oracle -------------------------
+
+def _mutants(blobs, rng, count):
+    out = []
+    for t in range(count):
+        b = bytearray(blobs[t % len(blobs)])
+        if t % 4 == 3:
+            b = b[: int(rng.integers(0, len(b)))]
+        else:
+            for _ in range(int(rng.integers(1, 4))):
+                if b:
+                    i = int(rng.integers(0, len(b)))
+                    b[i] ^= 1 << int(rng.integers(0, 8))
+        out.append(bytes(b))
+    return out
+
+
+@pytest.mark.parametrize("codec", [oracle.RLE_V1, oracle.RLE_V2, oracle.DEFLATE])
+def test_corrupt_streams_status_parity(dev, codec):
+    rng = np.random.default_rng(100 + codec)
+    if codec == oracle.DEFLATE:
+        vocab = workloads._vocab(0)
+        raw = [workloads.zipf_text(5000, rng, vocab), workloads.int32_column(6000, rng),
+               workloads.random_bytes(700, rng)]
+        base = [workloads.deflate_raw(raw[0]), workloads.deflate_raw(raw[1], fixed=True),
+                workloads.deflate_raw(raw[2], level=0)]
+        sizes = [len(r) for r in raw]
+    else:
+        ch0 = (workloads.rle_v1_workload if codec == oracle.RLE_V1 else workloads.rle_v2_workload)(
+            seed=9, n_values=6000, chunk_values=2000)
+        base = [ch0.comp[int(ch0.chunk_offsets[i]):int(ch0.chunk_offsets[i + 1])].tobytes() for i in range(3)]
+        sizes = [16000] * 3
+    muts = _mutants(base, rng, 600)
+    ch = _chunks(codec, muts, [sizes[t % len(sizes)] for t in range(len(muts))])
+    _say(f"corrupt codec={codec} chunks={ch.n_chunks}")
+    st = assert_parity(codec, ch, dev)
+    assert (st != 0).sum() > 100
+
+
+# ---- full workload sizes, benchmark launch configuration ---------------------
+
+def test_full_rle_v1(dev):
+    ch = workloads.rle_v1_workload(seed=0)
+    _say(f"full rle_v1 chunks={ch.n_chunks}")
+    assert (assert_parity(oracle.RLE_V1, ch, dev) == 0).all()
+
+
+def test_full_rle_v2(dev):
+    ch = workloads.rle_v2_workload(seed=0)
+    _say(f"full rle_v2 chunks={ch.n_chunks}")
+    assert (assert_parity(oracle.RLE_V2, ch, dev, threads=16) == 0).all()
+
+
+def test_full_deflate(dev):
+    ch = workloads.deflate_workload(seed=0)
+    _say(f"full deflate chunks={ch.n_chunks}")
+    assert (assert_parity(oracle.DEFLATE, ch, dev, threads=16) == 0).all()
