@@ -44,7 +44,7 @@ enum {
 
 /*
  * Tuning knobs; a zeroed struct (or NULL) selects the defaults.
- *   waves_per_block   wavefronts per workgroup, 1..16 (default 4); waves
+ *   waves_per_block   wavefronts per workgroup: 1, 2 or 4 (default 4); waves
  *                     never synchronize with each other, so this only
  *                     shapes occupancy and dispatch.
  *   lit_table_bits    Deflate literal/length lookup-table bits, 9..11

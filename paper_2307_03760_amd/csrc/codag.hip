@@ -16,43 +16,52 @@
 
 namespace codag {
 
-constexpr uint32_t kRleV1Lds = kRingLdsBytes + 128 * 4;  // ring + literal-list terminator slots
-constexpr uint32_t kRleV2Lds = kRingLdsBytes;
-
+// Per-wave LDS beyond the input ring and its landing buffer.
+template <int Codec, int TB>
+struct WaveScratch {
+    uint32_t unused;
+};
 template <int TB>
-constexpr uint32_t deflate_lds_bytes() {
-    return (uint32_t)((sizeof(DeflateLds<TB>) + 15) & ~size_t(15));
-}
+struct WaveScratch<CODAG_RLE_V1, TB> {
+    uint32_t ends[128];  // literal-list terminator positions
+};
+template <int TB>
+struct WaveScratch<CODAG_DEFLATE, TB> {
+    DeflateLds<TB> t;
+};
 
 __device__ __forceinline__ uint64_t error_key(uint64_t chunk, int st) {
     return (chunk << 4) | (uint64_t)(uint32_t)(-st);
 }
 
-// Decodes chunk c with the calling wave; returns its status.  `lds` is this
-// wave's LDS slice.
+// Decodes chunk c with the calling wave; returns its status.
 template <int Codec, int TB>
 __device__ __forceinline__ int decode_one(const uint8_t *comp, const uint64_t *coff, uint8_t *out,
-                                          const uint64_t *ooff, uint64_t c, uint8_t *lds) {
+                                          const uint64_t *ooff, uint64_t c, uint32_t *ring,
+                                          uint32_t *land, WaveScratch<Codec, TB> *scratch) {
     uint64_t i0 = coff[c], i1 = coff[c + 1], o0 = ooff[c], o1 = ooff[c + 1];
     if (i1 < i0 || o1 < o0 || i1 - i0 >= (1ull << 31) || o1 - o0 >= (1ull << 31))
         return CODAG_E_INVALID_ARGUMENT;
     uint32_t in_len = (uint32_t)(i1 - i0), out_len = (uint32_t)(o1 - o0);
     uint8_t *dst = out + o0;
     InRing in;
+    int st;
     if constexpr (Codec == CODAG_DEFLATE) {
-        auto *d = reinterpret_cast<DeflateLds<TB> *>(lds);
-        in.init(comp + i0, in_len, d->ring);
-        return decode_deflate<TB>(in, dst, out_len, d);
+        in.init(comp + i0, in_len, ring, land);
+        st = decode_deflate<TB>(in, dst, out_len, &scratch->t);
     } else {
         if ((out_len & 7) || (reinterpret_cast<uintptr_t>(dst) & 7)) return CODAG_E_INVALID_ARGUMENT;
-        in.init(comp + i0, in_len, reinterpret_cast<uint32_t *>(lds));
+        in.init(comp + i0, in_len, ring, land);
         uint64_t *dst64 = reinterpret_cast<uint64_t *>(dst);
         if constexpr (Codec == CODAG_RLE_V1)
-            return decode_rle_v1(in, dst64, out_len / 8,
-                                 reinterpret_cast<uint32_t *>(lds + kRingLdsBytes));
+            st = decode_rle_v1(in, dst64, out_len / 8, scratch->ends);
         else
-            return decode_rle_v2(in, dst64, out_len / 8);
+            st = decode_rle_v2(in, dst64, out_len / 8);
     }
+    // The landing buffer may still have a fetch in flight: let it land before
+    // the wave moves on or exits.
+    __builtin_amdgcn_s_waitcnt(0);
+    return st;
 }
 
 __device__ __forceinline__ void report(uint64_t c, int st, int32_t *status,
@@ -63,19 +72,22 @@ __device__ __forceinline__ void report(uint64_t c, int st, int32_t *status,
     }
 }
 
-// Plain launch: one chunk per wave, every chunk of one codec.
-template <int Codec, int TB>
-__global__ void __launch_bounds__(1024) decode_plain(const uint8_t *comp, const uint64_t *coff,
-                                                     uint8_t *out, const uint64_t *ooff, uint64_t n,
-                                                     uint32_t lds_per_wave, int32_t *status,
-                                                     unsigned long long *err, uint64_t *ticks) {
-    extern __shared__ __align__(16) uint8_t smem[];
+// Plain launch: one chunk per wave, WPB waves per workgroup, every chunk of
+// one codec.  Each wave's LDS is a slice of three distinct arrays so the
+// compiler can tell ring reads from landing-buffer fetches.
+template <int Codec, int TB, int WPB>
+__global__ void __launch_bounds__(kWave * WPB)
+    decode_plain(const uint8_t *comp, const uint64_t *coff, uint8_t *out, const uint64_t *ooff,
+                 uint64_t n, int32_t *status, unsigned long long *err, uint64_t *ticks) {
+    __shared__ __align__(16) uint32_t s_ring[WPB][kRingLdsWords];
+    __shared__ __align__(16) uint32_t s_land[WPB][kLandWords];
+    __shared__ __align__(16) WaveScratch<Codec, TB> s_scratch[WPB];
     uint32_t wave = uni(threadIdx.x / kWave);
-    uint32_t wpb = blockDim.x / kWave;
-    uint64_t c = (uint64_t)blockIdx.x * wpb + wave;
+    uint64_t c = (uint64_t)blockIdx.x * WPB + wave;
     if (c >= n) return;
     uint64_t t0 = ticks ? __builtin_amdgcn_s_memtime() : 0;
-    int st = decode_one<Codec, TB>(comp, coff, out, ooff, c, smem + wave * lds_per_wave);
+    int st = decode_one<Codec, TB>(comp, coff, out, ooff, c, s_ring[wave], s_land[wave],
+                                   &s_scratch[wave]);
     if (ticks && lane() == 0) ticks[c] = __builtin_amdgcn_s_memtime() - t0;
     report(c, st, status, err);
 }
@@ -118,24 +130,25 @@ int device_state(DeviceState **out) {
     return CODAG_OK;
 }
 
+template <int Codec, int TB, int WPB>
+int launch_wpb(const uint8_t *comp, const uint64_t *coff, uint8_t *out, const uint64_t *ooff,
+               uint64_t n, int32_t *status, unsigned long long *err, uint64_t *ticks,
+               hipStream_t stream) {
+    uint64_t grid = (n + WPB - 1) / WPB;
+    hipLaunchKernelGGL((decode_plain<Codec, TB, WPB>), dim3((uint32_t)grid), dim3(kWave * WPB), 0,
+                       stream, comp, coff, out, ooff, n, status, err, ticks);
+    return hipGetLastError() == hipSuccess ? CODAG_OK : CODAG_E_HIP;
+}
+
 template <int Codec, int TB>
 int launch_plain(const uint8_t *comp, const uint64_t *coff, uint8_t *out, const uint64_t *ooff,
                  uint64_t n, int wpb, int32_t *status, unsigned long long *err, uint64_t *ticks,
                  hipStream_t stream) {
-    uint32_t per_wave = Codec == CODAG_DEFLATE ? deflate_lds_bytes<TB>()
-                        : Codec == CODAG_RLE_V1 ? kRleV1Lds
-                                                : kRleV2Lds;
-    size_t shmem = (size_t)per_wave * wpb;
-    auto kern = decode_plain<Codec, TB>;
-    static std::once_flag once;
-    std::call_once(once, [&] {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    });
-    uint64_t grid = (n + wpb - 1) / wpb;
-    hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(kWave * wpb), shmem, stream, comp, coff,
-                       out, ooff, n, per_wave, status, err, ticks);
-    return hipGetLastError() == hipSuccess ? CODAG_OK : CODAG_E_HIP;
+    switch (wpb) {
+        case 1: return launch_wpb<Codec, TB, 1>(comp, coff, out, ooff, n, status, err, ticks, stream);
+        case 2: return launch_wpb<Codec, TB, 2>(comp, coff, out, ooff, n, status, err, ticks, stream);
+        default: return launch_wpb<Codec, TB, 4>(comp, coff, out, ooff, n, status, err, ticks, stream);
+    }
 }
 
 }  // namespace
@@ -152,7 +165,7 @@ int codag_decompress_ex(int codec, const uint8_t *comp_buf, const uint64_t *chun
     if (n_chunks > (1ull << 40)) return CODAG_E_INVALID_ARGUMENT;
     int wpb = opts && opts->waves_per_block ? opts->waves_per_block : 4;
     int tb = opts && opts->lit_table_bits ? opts->lit_table_bits : 10;
-    if (wpb < 1 || wpb > 16 || tb < 9 || tb > 11) return CODAG_E_INVALID_ARGUMENT;
+    if ((wpb != 1 && wpb != 2 && wpb != 4) || tb < 9 || tb > 11) return CODAG_E_INVALID_ARGUMENT;
     uint64_t *ticks = opts ? opts->chunk_ticks : nullptr;
     DeviceState *ds = nullptr;
     int st = device_state(&ds);

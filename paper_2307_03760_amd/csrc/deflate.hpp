@@ -141,10 +141,9 @@ __device__ __forceinline__ BuildResult build_table(const uint8_t *lens, uint32_t
     return r;
 }
 
-// Everything one wave keeps in LDS while inflating.
+// The Huffman tables one wave keeps in LDS while inflating.
 template <int TB>
 struct DeflateLds {
-    uint32_t ring[kRingLdsBytes / 4];
     uint32_t lit[1u << TB];
     uint32_t dist[256];  // 8-bit distance table; also the code-length table (7 bits)
     CodeMeta lit_meta, dist_meta;

@@ -1,16 +1,20 @@
-// input_stream / output_stream for one wavefront (CODAG Section IV-B, IV-E,
-// IV-F).
+// input_stream for one wavefront (CODAG Section IV-B, IV-E).
 //
-// Input (the "conditional A" refill of Section IV-A): the chunk's compressed
-// bytes reach the wave through a 2 KiB ring in LDS, filled 1 KiB at a time
-// by one coalesced 16-byte load per lane.  The next 1 KiB is always in
-// flight in registers while the current one is consumed, so the load latency
-// overlaps decoding.  Bytes past the end of the chunk read as zero.  Readers
-// see 32-bit words; the ring carries a copy of its first 16 bytes after its
-// end so any run of four consecutive words is contiguous.
+// The chunk's compressed bytes reach the wave through a 2 KiB ring in LDS,
+// refilled 1 KiB at a time (the "conditional A" refill of Section IV-A).
+// Each kilobyte is fetched by one 16-byte direct-to-LDS load per lane into a
+// separate landing buffer while the previous kilobyte is being decoded, and
+// moved into the ring when decoding crosses into it.  Keeping the in-flight
+// data out of vector registers matters on this architecture: one counter
+// tracks both loads and stores, so waiting on an in-flight register load
+// would also wait for every output store issued since.  The landing buffer
+// is only read when the ring advances, so the hot loop never waits on it.
 //
-// Positions are byte offsets from `gbase`, the chunk start rounded down to 16
-// bytes, and fit in 32 bits (chunks are below 2 GiB).
+// Bytes past the end of the chunk read as zero.  Readers see 32-bit words;
+// the ring carries a copy of its first 16 bytes after its end so any run of
+// four consecutive words is contiguous.  Positions are byte offsets from
+// `gbase`, the chunk start rounded down to 16 bytes, and fit in 32 bits
+// (chunks are below 2 GiB).
 #pragma once
 
 #include "wave.hpp"
@@ -19,38 +23,50 @@ namespace codag {
 
 constexpr uint32_t kRingBytes = 2048;
 constexpr uint32_t kRingWords = kRingBytes / 4;
-constexpr uint32_t kRingLdsBytes = kRingBytes + 16;  // + mirror of the first 16 bytes
-constexpr uint32_t kFetchBytes = 1024;                // 64 lanes x 16 bytes
+constexpr uint32_t kRingLdsWords = kRingWords + 4;  // + mirror of the first 16 bytes
+constexpr uint32_t kFetchBytes = 1024;              // 64 lanes x 16 bytes
+constexpr uint32_t kLandWords = kFetchBytes / 4;
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Wait until every vector memory operation of this wave has completed
+// (s_waitcnt vmcnt(0); the expcnt and lgkmcnt fields are left at their
+// maxima).  Direct-to-LDS fetches are not tracked by the compiler, so reads of
+// the landing buffer are preceded by this explicitly.
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0f70); }
 
 struct InRing {
     const uint8_t *gbase;  // 16-byte aligned
     uint32_t skip;         // chunk start relative to gbase (0..15)
     uint32_t gend;         // one past the chunk's last byte, relative to gbase
     uint32_t loaded;       // bytes [loaded - 2048, loaded) are in the ring
-    uint32_t *ring;        // this wave's LDS ring (kRingLdsBytes)
-    uint4 pend;            // this lane's 16 bytes of [loaded, loaded + 1024), in flight
+    uint32_t *ring;        // this wave's ring (kRingLdsWords words)
+    uint32_t *land;        // this wave's landing buffer (kLandWords words)
 
+    // Start fetching [loaded, loaded + 1024) into the landing buffer.
     __device__ __forceinline__ void issue() {
         uint32_t at = loaded + 16 * lane();
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (at < gend) v = *reinterpret_cast<const uint4 *>(gbase + at);
-        pend = v;
+        if (at < gend)
+            __builtin_amdgcn_global_load_lds(gbase + at, (lds_void *)land, 16, 0, 0);
     }
 
-    __device__ __forceinline__ void init(const uint8_t *chunk, uint32_t len, uint32_t *lds) {
+    __device__ __forceinline__ void init(const uint8_t *chunk, uint32_t len, uint32_t *ring_lds,
+                                         uint32_t *land_lds) {
         uintptr_t a = reinterpret_cast<uintptr_t>(chunk);
         gbase = reinterpret_cast<const uint8_t *>(a & ~(uintptr_t)15);
         skip = (uint32_t)(a & 15);
         gend = skip + len;
         loaded = 0;
-        ring = lds;
+        ring = ring_lds;
+        land = land_lds;
         issue();
     }
 
-    // Move the in-flight kilobyte into the ring and start loading the next.
+    // Move the landed kilobyte into the ring and start fetching the next.
     __device__ __forceinline__ void commit() {
         uint32_t at = loaded + 16 * lane();
-        uint4 v = pend;
+        wait_vm();
+        uint4 v = reinterpret_cast<const uint4 *>(land)[lane()];
         if (at + 16 > gend) {  // zero the bytes past the end of the chunk
             uint32_t valid = at < gend ? gend - at : 0;
             uint32_t w[4] = {v.x, v.y, v.z, v.w};
