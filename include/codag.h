@@ -47,8 +47,12 @@ enum {
  *   waves_per_block   wavefronts per workgroup: 1, 2 or 4 (default 4); waves
  *                     never synchronize with each other, so this only
  *                     shapes occupancy and dispatch.
- *   lit_table_bits    Deflate literal/length lookup-table bits, 9..11
+ *   lit_table_bits    Deflate literal/length lookup-table bits, 9 or 10
  *                     (default 10); longer codes take a slower path.
+ *   history_kib       Deflate history window kept in LDS per wave: 8, 16 or
+ *                     32 KiB (default 8).  Back-references reaching further
+ *                     read the already written output from HBM.  With 32 the
+ *                     workgroup holds one wave.
  *   chunk_ticks       optional device array (n_chunks uint64): receives each
  *                     chunk's decode time in shader clock cycles.
  */
@@ -56,7 +60,8 @@ typedef struct codag_opts {
     int waves_per_block;
     int lit_table_bits;
     uint64_t *chunk_ticks;
-    int reserved[8];
+    int history_kib;
+    int reserved[7];
 } codag_opts;
 
 /*

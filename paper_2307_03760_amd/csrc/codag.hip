@@ -17,17 +17,19 @@
 namespace codag {
 
 // Per-wave LDS beyond the input ring and its landing buffer.
-template <int Codec, int TB>
+// For Deflate, TB is the literal/length table bits and H the history
+// window bytes.
+template <int Codec, int TB, uint32_t H>
 struct WaveScratch {
     uint32_t unused;
 };
-template <int TB>
-struct WaveScratch<CODAG_RLE_V1, TB> {
+template <int TB, uint32_t H>
+struct WaveScratch<CODAG_RLE_V1, TB, H> {
     uint32_t ends[128];  // literal-list terminator positions
 };
-template <int TB>
-struct WaveScratch<CODAG_DEFLATE, TB> {
-    DeflateLds<TB> t;
+template <int TB, uint32_t H>
+struct WaveScratch<CODAG_DEFLATE, TB, H> {
+    DeflateLds<TB, H> t;
 };
 
 __device__ __forceinline__ uint64_t error_key(uint64_t chunk, int st) {
@@ -35,10 +37,10 @@ __device__ __forceinline__ uint64_t error_key(uint64_t chunk, int st) {
 }
 
 // Decodes chunk c with the calling wave; returns its status.
-template <int Codec, int TB>
+template <int Codec, int TB, uint32_t H>
 __device__ __forceinline__ int decode_one(const uint8_t *comp, const uint64_t *coff, uint8_t *out,
                                           const uint64_t *ooff, uint64_t c, uint32_t *ring,
-                                          uint32_t *land, WaveScratch<Codec, TB> *scratch) {
+                                          uint32_t *land, WaveScratch<Codec, TB, H> *scratch) {
     uint64_t i0 = coff[c], i1 = coff[c + 1], o0 = ooff[c], o1 = ooff[c + 1];
     if (i1 < i0 || o1 < o0 || i1 - i0 >= (1ull << 31) || o1 - o0 >= (1ull << 31))
         return CODAG_E_INVALID_ARGUMENT;
@@ -48,7 +50,7 @@ __device__ __forceinline__ int decode_one(const uint8_t *comp, const uint64_t *c
     int st;
     if constexpr (Codec == CODAG_DEFLATE) {
         in.init(comp + i0, in_len, ring, land);
-        st = decode_deflate<TB>(in, dst, out_len, &scratch->t);
+        st = decode_deflate<TB, H>(in, dst, out_len, &scratch->t);
     } else {
         if ((out_len & 7) || (reinterpret_cast<uintptr_t>(dst) & 7)) return CODAG_E_INVALID_ARGUMENT;
         in.init(comp + i0, in_len, ring, land);
@@ -75,19 +77,19 @@ __device__ __forceinline__ void report(uint64_t c, int st, int32_t *status,
 // Plain launch: one chunk per wave, WPB waves per workgroup, every chunk of
 // one codec.  Each wave's LDS is a slice of three distinct arrays so the
 // compiler can tell ring reads from landing-buffer fetches.
-template <int Codec, int TB, int WPB>
+template <int Codec, int TB, uint32_t H, int WPB>
 __global__ void __launch_bounds__(kWave * WPB)
     decode_plain(const uint8_t *comp, const uint64_t *coff, uint8_t *out, const uint64_t *ooff,
                  uint64_t n, int32_t *status, unsigned long long *err, uint64_t *ticks) {
     __shared__ __align__(16) uint32_t s_ring[WPB][kRingLdsWords];
     __shared__ __align__(16) uint32_t s_land[WPB][kLandWords];
-    __shared__ __align__(16) WaveScratch<Codec, TB> s_scratch[WPB];
+    __shared__ __align__(16) WaveScratch<Codec, TB, H> s_scratch[WPB];
     uint32_t wave = uni(threadIdx.x / kWave);
     uint64_t c = (uint64_t)blockIdx.x * WPB + wave;
     if (c >= n) return;
     uint64_t t0 = ticks ? __builtin_amdgcn_s_memtime() : 0;
-    int st = decode_one<Codec, TB>(comp, coff, out, ooff, c, s_ring[wave], s_land[wave],
-                                   &s_scratch[wave]);
+    int st = decode_one<Codec, TB, H>(comp, coff, out, ooff, c, s_ring[wave], s_land[wave],
+                                      &s_scratch[wave]);
     if (ticks && lane() == 0) ticks[c] = __builtin_amdgcn_s_memtime() - t0;
     report(c, st, status, err);
 }
@@ -130,25 +132,39 @@ int device_state(DeviceState **out) {
     return CODAG_OK;
 }
 
-template <int Codec, int TB, int WPB>
+template <int Codec, int TB, uint32_t H, int WPB>
 int launch_wpb(const uint8_t *comp, const uint64_t *coff, uint8_t *out, const uint64_t *ooff,
                uint64_t n, int32_t *status, unsigned long long *err, uint64_t *ticks,
                hipStream_t stream) {
     uint64_t grid = (n + WPB - 1) / WPB;
-    hipLaunchKernelGGL((decode_plain<Codec, TB, WPB>), dim3((uint32_t)grid), dim3(kWave * WPB), 0,
-                       stream, comp, coff, out, ooff, n, status, err, ticks);
+    hipLaunchKernelGGL((decode_plain<Codec, TB, H, WPB>), dim3((uint32_t)grid), dim3(kWave * WPB),
+                       0, stream, comp, coff, out, ooff, n, status, err, ticks);
     return hipGetLastError() == hipSuccess ? CODAG_OK : CODAG_E_HIP;
 }
 
-template <int Codec, int TB>
+template <int Codec, int TB, uint32_t H>
 int launch_plain(const uint8_t *comp, const uint64_t *coff, uint8_t *out, const uint64_t *ooff,
                  uint64_t n, int wpb, int32_t *status, unsigned long long *err, uint64_t *ticks,
                  hipStream_t stream) {
     switch (wpb) {
-        case 1: return launch_wpb<Codec, TB, 1>(comp, coff, out, ooff, n, status, err, ticks, stream);
-        case 2: return launch_wpb<Codec, TB, 2>(comp, coff, out, ooff, n, status, err, ticks, stream);
-        default: return launch_wpb<Codec, TB, 4>(comp, coff, out, ooff, n, status, err, ticks, stream);
+        case 1: return launch_wpb<Codec, TB, H, 1>(comp, coff, out, ooff, n, status, err, ticks, stream);
+        case 2: return launch_wpb<Codec, TB, H, 2>(comp, coff, out, ooff, n, status, err, ticks, stream);
+        default: return launch_wpb<Codec, TB, H, 4>(comp, coff, out, ooff, n, status, err, ticks, stream);
     }
+}
+
+template <int TB>
+int launch_deflate(const uint8_t *comp, const uint64_t *coff, uint8_t *out, const uint64_t *ooff,
+                   uint64_t n, int wpb, int hist_kib, int32_t *status, unsigned long long *err,
+                   uint64_t *ticks, hipStream_t stream) {
+    if (hist_kib == 16)
+        return launch_plain<CODAG_DEFLATE, TB, 16384>(comp, coff, out, ooff, n, wpb, status, err,
+                                                      ticks, stream);
+    if (hist_kib == 32)
+        return launch_wpb<CODAG_DEFLATE, TB, 32768, 1>(comp, coff, out, ooff, n, status, err,
+                                                       ticks, stream);
+    return launch_plain<CODAG_DEFLATE, TB, 8192>(comp, coff, out, ooff, n, wpb, status, err, ticks,
+                                                 stream);
 }
 
 }  // namespace
@@ -165,7 +181,10 @@ int codag_decompress_ex(int codec, const uint8_t *comp_buf, const uint64_t *chun
     if (n_chunks > (1ull << 40)) return CODAG_E_INVALID_ARGUMENT;
     int wpb = opts && opts->waves_per_block ? opts->waves_per_block : 4;
     int tb = opts && opts->lit_table_bits ? opts->lit_table_bits : 10;
-    if ((wpb != 1 && wpb != 2 && wpb != 4) || tb < 9 || tb > 11) return CODAG_E_INVALID_ARGUMENT;
+    int hist = opts && opts->history_kib ? opts->history_kib : 8;
+    if ((wpb != 1 && wpb != 2 && wpb != 4) || (tb != 9 && tb != 10) ||
+        (hist != 8 && hist != 16 && hist != 32))
+        return CODAG_E_INVALID_ARGUMENT;
     uint64_t *ticks = opts ? opts->chunk_ticks : nullptr;
     DeviceState *ds = nullptr;
     int st = device_state(&ds);
@@ -173,20 +192,17 @@ int codag_decompress_ex(int codec, const uint8_t *comp_buf, const uint64_t *chun
     hipStream_t s = static_cast<hipStream_t>(stream);
     switch (codec) {
         case CODAG_RLE_V1:
-            return launch_plain<CODAG_RLE_V1, 10>(comp_buf, chunk_offsets, out_buf, out_offsets,
-                                                  n_chunks, wpb, chunk_status, ds->err, ticks, s);
+            return launch_plain<CODAG_RLE_V1, 10, 0>(comp_buf, chunk_offsets, out_buf, out_offsets,
+                                                     n_chunks, wpb, chunk_status, ds->err, ticks, s);
         case CODAG_RLE_V2:
-            return launch_plain<CODAG_RLE_V2, 10>(comp_buf, chunk_offsets, out_buf, out_offsets,
-                                                  n_chunks, wpb, chunk_status, ds->err, ticks, s);
+            return launch_plain<CODAG_RLE_V2, 10, 0>(comp_buf, chunk_offsets, out_buf, out_offsets,
+                                                     n_chunks, wpb, chunk_status, ds->err, ticks, s);
         default:
             if (tb == 9)
-                return launch_plain<CODAG_DEFLATE, 9>(comp_buf, chunk_offsets, out_buf, out_offsets,
-                                                      n_chunks, wpb, chunk_status, ds->err, ticks, s);
-            if (tb == 11)
-                return launch_plain<CODAG_DEFLATE, 11>(comp_buf, chunk_offsets, out_buf, out_offsets,
-                                                       n_chunks, wpb, chunk_status, ds->err, ticks, s);
-            return launch_plain<CODAG_DEFLATE, 10>(comp_buf, chunk_offsets, out_buf, out_offsets,
-                                                   n_chunks, wpb, chunk_status, ds->err, ticks, s);
+                return launch_deflate<9>(comp_buf, chunk_offsets, out_buf, out_offsets, n_chunks,
+                                         wpb, hist, chunk_status, ds->err, ticks, s);
+            return launch_deflate<10>(comp_buf, chunk_offsets, out_buf, out_offsets, n_chunks, wpb,
+                                      hist, chunk_status, ds->err, ticks, s);
     }
 }
 

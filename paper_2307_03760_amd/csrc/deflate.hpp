@@ -1,14 +1,20 @@
 // Deflate (RFC 1951) decoding by one wavefront.
 //
 // CODAG (Section II-A, III) locates Deflate's cost in Huffman decoding and
-// dictionary copies.  Here the symbol chain is wave-uniform scalar code: a
-// 64-bit bit buffer in scalar registers, refilled one 32-bit word at a time
-// from the LDS input ring, and a lookup per symbol in LDS tables that the
-// whole wave builds in parallel for each block.  Literals are staged in a
-// vector register (one byte slot per lane byte, 256 bytes per wave) and
-// written out together ("write_byte" in Section IV-B); back-references are
-// copied by all lanes at once ("memcpy", Section IV-F), including the
-// overlapping case where the length exceeds the distance.
+// dictionary copies.  Here:
+//   * The symbol chain is wave-uniform scalar code: a 64-bit bit buffer in
+//     scalar registers, refilled one 32-bit word at a time from the LDS input
+//     ring, and one lookup per symbol in LDS tables that the whole wave builds
+//     in parallel for each block.
+//   * Output goes first to a per-wave history window in LDS (the last H bytes
+//     of output) and reaches HBM behind the decoder, 1 KiB at a time, as one
+//     16-byte store per lane of an aligned kilobyte ("coalesced on-demand
+//     writing", Section IV-F).  Literals ("write_byte") are one LDS byte write
+//     each; back-references ("memcpy", Section IV-F) are copied by all lanes
+//     at once from the window, including the overlapping case where the
+//     length exceeds the distance.  Only a reference reaching further back
+//     than the window reads HBM.  Reading just-written output from HBM would
+//     make each copy wait for all outstanding stores of the wave.
 #pragma once
 
 #include "../../include/codag.h"
@@ -16,44 +22,50 @@
 
 namespace codag {
 
-// Table entry: bits 0-3 code length, 4-7 extra bits, 8-10 kind, 16-31 value.
+// Table entry (16 bits): bits 0-3 code length, 4-12 symbol, 13-15 kind.
 enum : uint32_t {
-    kLit = 0,     // literal byte
-    kBase = 1,    // length or distance: value = base, plus `extra` bits
-    kEob = 2,     // end of block
-    kSlow = 3,    // code longer than the table: canonical decode
-    kInvalid = 4, // no code starts with these bits
-    kBadSym = 5,  // a code for a symbol that may not appear (286, 287; 30, 31)
-    kSym = 6,     // code-length alphabet symbol
+    kLit = 0,      // literal byte (symbol 0..255)
+    kBase = 1,     // length symbol 257..285, or distance symbol 0..29
+    kEob = 2,      // end of block
+    kSlow = 3,     // code longer than the table: canonical decode
+    kInvalid = 4,  // no code starts with these bits
+    kBadSym = 5,   // a code for a symbol that may not appear (286, 287; 30, 31)
+    kSym = 6,      // code-length alphabet symbol
 };
 
-__device__ __forceinline__ uint32_t entry(uint32_t kind, uint32_t len, uint32_t extra, uint32_t value) {
-    return len | (extra << 4) | (kind << 8) | (value << 16);
+__device__ __forceinline__ uint32_t entry16(uint32_t kind, uint32_t len, uint32_t sym) {
+    return len | (sym << 4) | (kind << 13);
 }
 
 enum TableUse { kLitLen = 0, kDist = 1, kCodeLen = 2 };
 
-// The symbol's meaning, from RFC 1951 section 3.2.5.
-__device__ __forceinline__ uint32_t symbol_entry(int use, uint32_t s, uint32_t len) {
-    if (use == kCodeLen) return entry(kSym, len, 0, s);
-    if (use == kLitLen) {
-        if (s < 256) return entry(kLit, len, 0, s);
-        if (s == 256) return entry(kEob, len, 0, 0);
-        if (s > 285) return entry(kBadSym, len, 0, 0);
-        if (s == 285) return entry(kBase, len, 0, 258);
-        uint32_t k = s - 257;
-        if (k < 8) return entry(kBase, len, 0, k + 3);
-        uint32_t e = (k >> 2) - 1;
-        return entry(kBase, len, e, ((4 + (k & 3)) << e) + 3);
-    }
-    if (s > 29) return entry(kBadSym, len, 0, 0);
-    if (s < 4) return entry(kBase, len, 0, s + 1);
-    uint32_t e = (s >> 1) - 1;
-    return entry(kBase, len, e, ((2 + (s & 1)) << e) + 1);
+__device__ __forceinline__ uint32_t symbol_kind(int use, uint32_t s) {
+    if (use == kCodeLen) return kSym;
+    if (use == kLitLen) return s < 256 ? kLit : s == 256 ? kEob : s <= 285 ? kBase : kBadSym;
+    return s <= 29 ? kBase : kBadSym;
 }
 
-// Per-code metadata kept for the slow path: count, first code and offset
-// into `sorted` for each code length 1..15.
+// Base value and extra-bit count of length symbols 257..285 (lane k holds
+// symbol 257 + k) and distance symbols 0..29 (lane k holds symbol k), packed
+// as base | extra << 16 (RFC 1951 section 3.2.5).
+__device__ __forceinline__ uint32_t length_lane_table() {
+    uint32_t k = lane();
+    if (k >= 29) return 0;
+    if (k == 28) return 258;
+    if (k < 8) return k + 3;
+    uint32_t e = (k >> 2) - 1;
+    return (((4 + (k & 3)) << e) + 3) | (e << 16);
+}
+__device__ __forceinline__ uint32_t distance_lane_table() {
+    uint32_t k = lane();
+    if (k >= 30) return 0;
+    if (k < 4) return k + 1;
+    uint32_t e = (k >> 1) - 1;
+    return (((2 + (k & 1)) << e) + 1) | (e << 16);
+}
+
+// Per-code metadata for the slow path: count, first code and offset into
+// `sorted` for each code length 1..15.
 struct CodeMeta {
     uint32_t count[16];
     uint32_t first[16];
@@ -66,10 +78,12 @@ struct BuildResult {
     uint32_t ones;   // number of codes of length 1
 };
 
-// Builds the lookup table (2^tb entries) for the canonical code whose
-// lengths are lens[0..n) (n <= 320), lane-parallel.
-__device__ __forceinline__ BuildResult build_table(const uint8_t *lens, uint32_t n, uint32_t tb, int use,
-                                   uint32_t *tab, uint16_t *sorted, CodeMeta *meta) {
+// Builds the lookup table (2^tb entries) of the canonical code whose lengths
+// are lens[0..n) (n <= 320), lane-parallel: per-length counts and each
+// symbol's rank come from ballots, then every symbol fills its table slots.
+__device__ __forceinline__ BuildResult build_table(const uint8_t *lens, uint32_t n, uint32_t tb,
+                                                   int use, uint16_t *tab, uint16_t *sorted,
+                                                   CodeMeta *meta) {
     const uint32_t l = lane();
     uint32_t cnt[16];
 #pragma unroll
@@ -117,7 +131,7 @@ __device__ __forceinline__ BuildResult build_table(const uint8_t *lens, uint32_t
         meta->offs[l] = o;
     }
     if (left > 0) {  // incomplete: codes not in the set are invalid
-        for (uint32_t i = l; i < (1u << tb); i += kWave) tab[i] = entry(kInvalid, 0, 0, 0);
+        for (uint32_t i = l; i < (1u << tb); i += kWave) tab[i] = (uint16_t)entry16(kInvalid, 0, 0);
     }
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -129,11 +143,11 @@ __device__ __forceinline__ BuildResult build_table(const uint8_t *lens, uint32_t
             sorted[meta->offs[m] + rank[p]] = (uint16_t)s;
             if (m <= tb) {
                 uint32_t rev = __builtin_bitreverse32(code) >> (32 - m);
-                uint32_t e = symbol_entry(use, s, m);
+                uint16_t e = (uint16_t)entry16(symbol_kind(use, s), m, s);
                 for (uint32_t k = 0; k < (1u << (tb - m)); k++) tab[rev | (k << m)] = e;
             } else {
                 uint32_t prefix = code >> (m - tb);
-                tab[__builtin_bitreverse32(prefix) >> (32 - tb)] = entry(kSlow, 0, 0, 0);
+                tab[__builtin_bitreverse32(prefix) >> (32 - tb)] = (uint16_t)entry16(kSlow, 0, 0);
             }
         }
     }
@@ -141,29 +155,32 @@ __device__ __forceinline__ BuildResult build_table(const uint8_t *lens, uint32_t
     return r;
 }
 
-// The Huffman tables one wave keeps in LDS while inflating.
-template <int TB>
+constexpr uint32_t kDistBits = 8;
+constexpr uint32_t kCodeLenBits = 7;
+
+// Order in which the code-length code's lengths are sent (RFC 1951 3.2.7).
+__constant__ const uint8_t kCodeLenOrder[19] = {16, 17, 18, 0, 8,  7, 9,  6, 10, 5,
+                                                11, 4,  12, 3, 13, 2, 14, 1, 15};
+
+// What one wave keeps in LDS while inflating, besides the input ring: the
+// Huffman tables and the output history window.
+template <int TB, uint32_t H>
 struct DeflateLds {
-    uint32_t lit[1u << TB];
-    uint32_t dist[256];  // 8-bit distance table; also the code-length table (7 bits)
+    uint8_t window[H];  // output byte at absolute address a lives at window[a % H]
+    uint16_t lit[1u << TB];
+    uint16_t dist[1u << kDistBits];  // also the code-length table (7 bits)
     CodeMeta lit_meta, dist_meta;
     uint16_t lit_sorted[288];
     uint16_t dist_sorted[32];
     uint8_t lens[320];
 };
-constexpr uint32_t kDistBits = 8;
-
-// Order in which the code-length code's lengths are sent (RFC 1951 3.2.7).
-__constant__ const uint8_t kCodeLenOrder[19] = {16, 17, 18, 0, 8,  7, 9,  6, 10, 5,
-                                                11, 4,  12, 3, 13, 2, 14, 1, 15};
-constexpr uint32_t kCodeLenBits = 7;
 
 // Wave-uniform LSB-first bit reader over the ring.
 struct BitIn {
-    uint64_t buf;     // valid bits are the low `cnt`
+    uint64_t buf;    // valid bits are the low `cnt`
     uint32_t cnt;
-    uint32_t next;    // byte position of the next (aligned) word to load
-    int64_t remain;   // input bits not yet consumed (negative: past the end)
+    uint32_t next;   // byte position of the next (aligned) word to load
+    int64_t remain;  // input bits not yet consumed (negative: past the end)
 
     __device__ __forceinline__ void seek(InRing &in, uint32_t pos) {
         if (pos >= in.loaded + kFetchBytes) in.restart(pos);
@@ -209,133 +226,144 @@ __device__ __forceinline__ uint32_t slow_symbol(const BitIn &bi, const CodeMeta 
         uint32_t c = uni(meta->count[len]), f = uni(meta->first[len]);
         if (code - f < c) {
             uint32_t s = uni((uint32_t)sorted[uni(meta->offs[len]) + code - f]);
-            return symbol_entry(use, s, len);
+            return entry16(symbol_kind(use, s), len, s);
         }
     }
-    return entry(kInvalid, 0, 0, 0);
+    return entry16(kInvalid, 0, 0);
 }
 
-// Output side: staged literals plus direct byte-range writes.
-struct ByteOut {
-    uint8_t *base;    // the chunk's output range
-    uint32_t cap;
-    uint32_t pos;     // bytes produced (staged ones included)
-    uint32_t spos;    // position of the first staged byte
-    uint32_t stage;   // this lane's 4 staged bytes (slot = pos - spos)
+// Output through the LDS history window.  Bytes at absolute addresses below
+// `fa` (a multiple of 1 KiB) are in HBM; bytes in [fa, ob + pos) only in the
+// window.  `room` = fa + H - (ob + pos): bytes that can be appended before the
+// oldest unflushed kilobyte must go out.
+template <uint32_t H>
+struct WindowOut {
+    uint8_t *ob;      // the chunk's output range in HBM
+    uint8_t *win;     // the wave's window (H bytes, LDS)
+    uint64_t oabs;    // ob as an integer
+    uint64_t fa;
+    uint32_t cap, pos, room;
 
-    __device__ __forceinline__ void flush() {
-        uint32_t n = pos - spos;
-        if (n == 0) return;
-        uint32_t j = 4 * lane();
-        if (j < n) store_bytes(base + spos + j, stage, min(4u, n - j));
-        spos = pos;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __device__ __forceinline__ void init(uint8_t *out, uint32_t capacity, uint8_t *window) {
+        ob = out;
+        win = window;
+        oabs = reinterpret_cast<uintptr_t>(out);
+        fa = oabs & ~(uint64_t)1023;
+        cap = capacity;
+        pos = 0;
+        room = (uint32_t)(fa + H - oabs);
+    }
+    __device__ __forceinline__ uint32_t slot(uint64_t a) const { return (uint32_t)a & (H - 1); }
+
+    // Writes the kilobyte [fa, fa + 1024) to HBM, restricted to the bytes of
+    // the chunk's range below `limit` (an absolute address).
+    __device__ __forceinline__ void flush_block(uint64_t limit) {
+        uint64_t a = fa + 16 * lane();
+        uint32_t sl = slot(a);
+        if (a >= oabs && a + 16 <= limit) {
+            *reinterpret_cast<uint4 *>(reinterpret_cast<uint8_t *>(a)) =
+                *reinterpret_cast<const uint4 *>(win + sl);
+        } else if (a + 16 > oabs && a < limit) {
+            for (uint32_t k = 0; k < 16; k++)
+                if (a + k >= oabs && a + k < limit) reinterpret_cast<uint8_t *>(a)[k] = win[sl + k];
+        }
+        fa += 1024;
+    }
+    __device__ __forceinline__ void make_room(uint32_t len) {
+        while (room < len) {
+            flush_block(oabs + cap);
+            room += 1024;
+        }
     }
     __device__ __forceinline__ void put_literal(uint32_t b) {
-        uint32_t slot = pos - spos;
-        uint32_t sh = 8 * (slot & 3);
-        if (lane() == (slot >> 2)) stage = (stage & ~(0xffu << sh)) | (b << sh);
+        make_room(1);
+        if (lane() == 0) win[slot(oabs + pos)] = (uint8_t)b;
         pos++;
-        if (pos - spos == 4 * kWave) flush();
+        room--;
     }
-    // Back-reference: len bytes from dist bytes back (dist <= pos).  Bytes
-    // repeat with period dist when len > dist.
+    // Back-reference: len bytes from dist bytes back (dist <= pos).  With
+    // len > dist the bytes repeat with period dist.
     __device__ __forceinline__ void copy(uint32_t dist, uint32_t len) {
-        flush();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        uint8_t *dst = base + pos;
-        const uint8_t *src = base + pos - dist;
-        if (dist >= len) {
-            for (uint32_t i = lane(); i < len; i += kWave) dst[i] = src[i];
-        } else {
-            uint32_t r = lane() % dist, step = kWave % dist;
-            for (uint32_t i = lane(); i < len; i += kWave) {
-                dst[i] = src[r];
+        make_room(len);
+        uint64_t dst = oabs + pos;
+        uint64_t lds_from = dst + len - H;  // older bytes may be overwritten below
+        bool near = dist + len <= H;
+        uint32_t r = 0, step = 0;
+        if (dist < len) {
+            r = lane() % dist;
+            step = kWave % dist;
+        }
+        for (uint32_t i = lane(); i < len; i += kWave) {
+            uint64_t q = dst - dist + (dist < len ? r : i);
+            uint8_t b;
+            if (near || q >= lds_from) {
+                b = win[slot(q)];
+            } else {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                b = *reinterpret_cast<const uint8_t *>(q);
+            }
+            win[slot(dst + i)] = b;
+            if (dist < len) {
                 r += step;
                 if (r >= dist) r -= dist;
             }
         }
         pos += len;
-        spos = pos;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        room -= len;
+    }
+    // Writes every byte produced so far to HBM.
+    __device__ __forceinline__ void finish() {
+        uint64_t end = oabs + pos;
+        while (fa < end) flush_block(end);
     }
 };
 
-// Copies len bytes from global input to the output (stored blocks).
-__device__ __forceinline__ void copy_stored(uint8_t *dst, const uint8_t *src, uint32_t len) {
-    const uint32_t l = lane();
-    // Head: bring the destination to a 4-byte boundary.
-    uint32_t head = (uint32_t)((4 - ((uintptr_t)dst & 3)) & 3);
-    if (head > len) head = len;
-    if (l < head) dst[l] = src[l];
-    dst += head;
-    src += head;
-    len -= head;
-    uint32_t words = len >> 2;
-    uint32_t a = (uint32_t)((uintptr_t)src & 3);
-    const uint32_t *s4 = reinterpret_cast<const uint32_t *>(src - a);
-    uint32_t *d4 = reinterpret_cast<uint32_t *>(dst);
-    for (uint32_t k0 = 0; k0 < words; k0 += 4 * kWave) {
-        uint32_t v[4];
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            uint32_t k = k0 + j * kWave + l;
-            if (k < words) {
-                uint32_t lo = s4[k];
-                uint32_t hi = a ? s4[k + 1] : 0;
-                v[j] = a ? __builtin_amdgcn_alignbyte(hi, lo, a) : lo;
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            uint32_t k = k0 + j * kWave + l;
-            if (k < words) d4[k] = v[j];
-        }
-    }
-    uint32_t tail = len & 3, t0 = words * 4;
-    if (l < tail) dst[t0 + l] = src[t0 + l];
-}
-
-template <int TB>
-__device__ __forceinline__ int decode_deflate(InRing &in, uint8_t *out, uint32_t cap, DeflateLds<TB> *lds) {
+template <int TB, uint32_t H>
+__device__ __forceinline__ int decode_deflate(InRing &in, uint8_t *out, uint32_t cap,
+                                              DeflateLds<TB, H> *lds) {
     const uint32_t l = lane();
     BitIn bi;
     bi.seek(in, in.skip);
-    ByteOut o;
-    o.base = out;
-    o.cap = cap;
-    o.pos = 0;
-    o.spos = 0;
-    o.stage = 0;
+    WindowOut<H> o;
+    o.init(out, cap, lds->window);
+    const uint32_t len_tab = length_lane_table(), dist_tab = distance_lane_table();
     bool fixed_ready = false;
-    uint32_t lmask = (1u << TB) - 1, dmask = (1u << kDistBits) - 1;
     bool have_dist = true;
+    int st = CODAG_OK;
 
     for (;;) {
         bi.refill(in);
         uint32_t hdr = bi.peek(3);
-        if (!bi.drop(3)) return CODAG_E_TRUNCATED;
+        if (!bi.drop(3)) { st = CODAG_E_TRUNCATED; break; }
         uint32_t btype = hdr >> 1;
         bool last = hdr & 1;
         if (btype == 0) {
             // Stored block: byte-align, LEN, NLEN = ~LEN, then LEN raw bytes.
-            uint32_t pad = bi.cnt & 7;
-            bi.drop(pad);
+            bi.drop(bi.cnt & 7);
             bi.refill(in);
             uint32_t len = bi.peek(16), nlen = (uint32_t)(bi.buf >> 16) & 0xffff;
-            if (!bi.drop(32)) return CODAG_E_TRUNCATED;
-            if (nlen != (~len & 0xffff)) return CODAG_E_CORRUPT;
-            if (o.pos + len > cap) return CODAG_E_OVERFLOW;
+            if (!bi.drop(32)) { st = CODAG_E_TRUNCATED; break; }
+            if (nlen != (~len & 0xffff)) { st = CODAG_E_CORRUPT; break; }
+            if (o.pos + len > cap) { st = CODAG_E_OVERFLOW; break; }
             uint32_t p = bi.byte_pos();
-            if (p + len > in.gend) return CODAG_E_TRUNCATED;
-            o.flush();
-            copy_stored(o.base + o.pos, in.gbase + p, len);
-            o.pos += len;
-            o.spos = o.pos;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (p + len > in.gend) { st = CODAG_E_TRUNCATED; break; }
+            for (uint32_t done = 0; done < len;) {
+                uint32_t piece = min(len - done, 512u);
+                o.make_room(piece);
+                in.ensure(p + done + piece + 4);
+                uint64_t dst = o.oabs + o.pos;
+                for (uint32_t i = l; i < piece; i += kWave) {
+                    uint32_t q = p + done + i;
+                    o.win[o.slot(dst + i)] = (uint8_t)(in.word(q >> 2) >> (8 * (q & 3)));
+                }
+                o.pos += piece;
+                o.room -= piece;
+                done += piece;
+            }
             bi.seek(in, p + len);
         } else if (btype == 3) {
-            return CODAG_E_CORRUPT;
+            st = CODAG_E_CORRUPT;
+            break;
         } else {
             if (btype == 1) {
                 if (!fixed_ready) {
@@ -357,26 +385,28 @@ __device__ __forceinline__ int decode_deflate(InRing &in, uint8_t *out, uint32_t
                 uint32_t hlit = bi.peek(5) + 257;
                 uint32_t hdist = ((uint32_t)(bi.buf >> 5) & 31) + 1;
                 uint32_t hclen = ((uint32_t)(bi.buf >> 10) & 15) + 4;
-                if (!bi.drop(14)) return CODAG_E_TRUNCATED;
-                if (hlit > 286 || hdist > 30) return CODAG_E_CORRUPT;
+                if (!bi.drop(14)) { st = CODAG_E_TRUNCATED; break; }
+                if (hlit > 286 || hdist > 30) { st = CODAG_E_CORRUPT; break; }
                 if (l < 19) lds->lens[l] = 0;
                 __builtin_amdgcn_wave_barrier();
+                bool trunc = false;
                 for (uint32_t i = 0; i < hclen; i++) {
                     bi.refill(in);
                     uint32_t v = bi.peek(3);
-                    if (!bi.drop(3)) return CODAG_E_TRUNCATED;
+                    if (!bi.drop(3)) { trunc = true; break; }
                     if (l == 0) lds->lens[kCodeLenOrder[i]] = (uint8_t)v;
                 }
+                if (trunc) { st = CODAG_E_TRUNCATED; break; }
                 __builtin_amdgcn_wave_barrier();
                 BuildResult cl = build_table(lds->lens, 19, kCodeLenBits, kCodeLen, lds->dist,
                                              lds->dist_sorted, &lds->dist_meta);
-                if (cl.left != 0) return CODAG_E_CORRUPT;
+                if (cl.left != 0) { st = CODAG_E_CORRUPT; break; }
                 uint32_t idx = 0, total = hlit + hdist, prev = 0;
                 while (idx < total) {
                     bi.refill(in);
-                    uint32_t e = uni(lds->dist[bi.peek(kCodeLenBits)]);
-                    uint32_t sym = e >> 16;
-                    if (!bi.drop(e & 15)) return CODAG_E_TRUNCATED;
+                    uint32_t e = uni((uint32_t)lds->dist[bi.peek(kCodeLenBits)]);
+                    uint32_t sym = (e >> 4) & 511;
+                    if (!bi.drop(e & 15)) { st = CODAG_E_TRUNCATED; break; }
                     if (sym < 16) {
                         if (l == 0) lds->lens[idx] = (uint8_t)sym;
                         prev = sym;
@@ -385,80 +415,90 @@ __device__ __forceinline__ int decode_deflate(InRing &in, uint8_t *out, uint32_t
                     }
                     uint32_t rep, val;
                     if (sym == 16) {
-                        if (idx == 0) return CODAG_E_CORRUPT;
+                        if (idx == 0) { st = CODAG_E_CORRUPT; break; }
                         rep = 3 + bi.peek(2);
-                        if (!bi.drop(2)) return CODAG_E_TRUNCATED;
+                        if (!bi.drop(2)) { st = CODAG_E_TRUNCATED; break; }
                         val = prev;
                     } else if (sym == 17) {
                         rep = 3 + bi.peek(3);
-                        if (!bi.drop(3)) return CODAG_E_TRUNCATED;
+                        if (!bi.drop(3)) { st = CODAG_E_TRUNCATED; break; }
                         val = 0;
                     } else {
                         rep = 11 + bi.peek(7);
-                        if (!bi.drop(7)) return CODAG_E_TRUNCATED;
+                        if (!bi.drop(7)) { st = CODAG_E_TRUNCATED; break; }
                         val = 0;
                     }
-                    if (idx + rep > total) return CODAG_E_CORRUPT;
+                    if (idx + rep > total) { st = CODAG_E_CORRUPT; break; }
                     for (uint32_t k = l; k < rep; k += kWave) lds->lens[idx + k] = (uint8_t)val;
                     prev = val;
                     idx += rep;
                 }
+                if (st) break;
                 __builtin_amdgcn_wave_barrier();
-                if (uni((uint32_t)lds->lens[256]) == 0) return CODAG_E_CORRUPT;
+                if (uni((uint32_t)lds->lens[256]) == 0) { st = CODAG_E_CORRUPT; break; }
                 BuildResult lr = build_table(lds->lens, hlit, TB, kLitLen, lds->lit, lds->lit_sorted,
                                              &lds->lit_meta);
-                if (lr.left < 0 || (lr.left > 0 && !(lr.total == 1 && lr.ones == 1)))
-                    return CODAG_E_CORRUPT;
+                if (lr.left < 0 || (lr.left > 0 && !(lr.total == 1 && lr.ones == 1))) {
+                    st = CODAG_E_CORRUPT;
+                    break;
+                }
                 BuildResult dr = build_table(lds->lens + hlit, hdist, kDistBits, kDist, lds->dist,
                                              lds->dist_sorted, &lds->dist_meta);
-                if (dr.left < 0 || (dr.left > 0 && dr.total != 0 && !(dr.total == 1 && dr.ones == 1)))
-                    return CODAG_E_CORRUPT;
+                if (dr.left < 0 || (dr.left > 0 && dr.total != 0 && !(dr.total == 1 && dr.ones == 1))) {
+                    st = CODAG_E_CORRUPT;
+                    break;
+                }
                 have_dist = dr.total != 0;
             }
             // Symbols until end of block.
             for (;;) {
                 bi.refill(in);
-                uint32_t e = uni(lds->lit[bi.peek(TB)]);
-                uint32_t kind = (e >> 8) & 7;
+                uint32_t e = uni((uint32_t)lds->lit[bi.peek(TB)]);
+                uint32_t kind = e >> 13;
                 if (kind == kSlow) {
                     e = slow_symbol(bi, &lds->lit_meta, lds->lit_sorted, kLitLen);
-                    kind = (e >> 8) & 7;
+                    kind = e >> 13;
                 }
-                if (kind == kInvalid) return CODAG_E_CORRUPT;
-                if (!bi.drop(e & 15)) return CODAG_E_TRUNCATED;
+                if (kind == kInvalid) { st = CODAG_E_CORRUPT; break; }
+                if (!bi.drop(e & 15)) { st = CODAG_E_TRUNCATED; break; }
+                uint32_t sym = (e >> 4) & 511;
                 if (kind == kLit) {
-                    if (o.pos >= cap) return CODAG_E_OVERFLOW;
-                    o.put_literal(e >> 16);
+                    if (o.pos >= cap) { st = CODAG_E_OVERFLOW; break; }
+                    o.put_literal(sym);
                     continue;
                 }
                 if (kind == kEob) break;
-                if (kind == kBadSym) return CODAG_E_CORRUPT;
+                if (kind == kBadSym) { st = CODAG_E_CORRUPT; break; }
                 // Length, then distance.
-                uint32_t ex = (e >> 4) & 15;
-                uint32_t len = (e >> 16) + bi.peek(ex);
-                if (!bi.drop(ex)) return CODAG_E_TRUNCATED;
-                if (!have_dist) return CODAG_E_CORRUPT;
+                uint32_t lb = readlane(len_tab, sym - 257);
+                uint32_t ex = lb >> 16;
+                uint32_t len = (lb & 0xffff) + bi.peek(ex);
+                if (!bi.drop(ex)) { st = CODAG_E_TRUNCATED; break; }
+                if (!have_dist) { st = CODAG_E_CORRUPT; break; }
                 bi.refill(in);
-                uint32_t d = uni(lds->dist[bi.peek(kDistBits)]);
-                uint32_t dk = (d >> 8) & 7;
+                uint32_t d = uni((uint32_t)lds->dist[bi.peek(kDistBits)]);
+                uint32_t dk = d >> 13;
                 if (dk == kSlow) {
                     d = slow_symbol(bi, &lds->dist_meta, lds->dist_sorted, kDist);
-                    dk = (d >> 8) & 7;
+                    dk = d >> 13;
                 }
-                if (dk == kInvalid) return CODAG_E_CORRUPT;
-                if (!bi.drop(d & 15)) return CODAG_E_TRUNCATED;
-                if (dk == kBadSym) return CODAG_E_CORRUPT;
-                uint32_t dex = (d >> 4) & 15;
-                uint32_t dist = (d >> 16) + bi.peek(dex);
-                if (!bi.drop(dex)) return CODAG_E_TRUNCATED;
-                if (dist > o.pos) return CODAG_E_CORRUPT;
-                if (o.pos + len > cap) return CODAG_E_OVERFLOW;
+                if (dk == kInvalid) { st = CODAG_E_CORRUPT; break; }
+                if (!bi.drop(d & 15)) { st = CODAG_E_TRUNCATED; break; }
+                if (dk == kBadSym) { st = CODAG_E_CORRUPT; break; }
+                uint32_t db = readlane(dist_tab, (d >> 4) & 31);
+                uint32_t dex = db >> 16;
+                uint32_t dist = (db & 0xffff) + bi.peek(dex);
+                if (!bi.drop(dex)) { st = CODAG_E_TRUNCATED; break; }
+                if (dist > o.pos) { st = CODAG_E_CORRUPT; break; }
+                if (o.pos + len > cap) { st = CODAG_E_OVERFLOW; break; }
                 o.copy(dist, len);
             }
+            if (st) break;
         }
         if (last) break;
     }
-    o.flush();
+    o.finish();
+    if (st) return st;
     return o.pos == cap ? CODAG_OK : CODAG_E_UNDERFLOW;
 }
 

@@ -198,6 +198,46 @@ __device__ __forceinline__ void ensure_packed_batch(InRing &in, uint32_t sec, ui
     in.ensure(sec + (uint32_t)((last_bit + 7) >> 3) + 12);
 }
 
+// A stretch of SHORT_REPEAT runs starting at pos.  Every lane decodes the
+// 64-byte window as if a SHORT_REPEAT header started at its own byte (width,
+// count and value from the following bytes); the wave then walks the chain of
+// runs from lane 0, pulling each run's fields out with readlane instead of a
+// round trip to LDS per run.  Stops at the first header that is not a
+// SHORT_REPEAT, past the window, at the end of input or when the output is
+// full, leaving pos at the next unread header.
+__device__ __forceinline__ int rle_v2_short_repeats(InRing &in, uint32_t &pos, uint32_t end,
+                                                    uint64_t *out, uint64_t &n, uint64_t cap) {
+    in.ensure(pos + 80);
+    uint64_t lo, hi;
+    ring_read16(in, pos + lane(), lo, hi);
+    uint32_t h = (uint32_t)(lo & 0xff);
+    uint32_t w = ((h >> 3) & 7) + 1;
+    uint64_t vbytes = (lo >> 8) | (hi << 56);
+    uint64_t v = unzigzag(__builtin_bswap64(vbytes) >> (64 - 8 * w));
+    uint32_t s = 0;
+    int st = CODAG_OK;
+    while (s < 64 && pos + s < end) {
+        uint32_t hs = readlane(h, s);
+        if (hs >> 6) break;  // not a SHORT_REPEAT header
+        uint32_t ws = ((hs >> 3) & 7) + 1, cs = (hs & 7) + 3;
+        if (n + cs > cap) {
+            st = CODAG_E_OVERFLOW;
+            break;
+        }
+        if (pos + s + 1 + ws > end) {
+            st = CODAG_E_TRUNCATED;
+            break;
+        }
+        uint64_t vs = readlane64(v, s);
+        if (lane() < cs) out[n + lane()] = vs;
+        n += cs;
+        s += 1 + ws;
+        if (n >= cap) break;
+    }
+    pos += s;
+    return st;
+}
+
 __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint64_t cap) {
     uint32_t pos = in.skip, end = in.gend;
     uint64_t n = 0;
@@ -209,13 +249,8 @@ __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint64_t
         uint32_t b0 = (uint32_t)(x & 0xff), type = b0 >> 6;
         if (type == 0) {
             // SHORT_REPEAT: byte width and count in the header, then the value.
-            uint32_t w = ((b0 >> 3) & 7) + 1, len = (b0 & 7) + 3;
-            if (n + len > cap) return CODAG_E_OVERFLOW;
-            if (pos + 1 + w > end) return CODAG_E_TRUNCATED;
-            uint64_t v = unzigzag(bytes_be(in.peek8(pos + 1), w));
-            if (l < len) out[n + l] = v;
-            pos += 1 + w;
-            n += len;
+            int st = rle_v2_short_repeats(in, pos, end, out, n, cap);
+            if (st) return st;
             continue;
         }
         if (pos + 2 > end) return CODAG_E_TRUNCATED;

@@ -54,7 +54,7 @@ def test_rle_v2_small(dev, wpb):
     assert (assert_parity(oracle.RLE_V2, ch, dev, waves_per_block=wpb) == 0).all()
 
 
-@pytest.mark.parametrize("tb", [9, 10, 11])
+@pytest.mark.parametrize("tb", [9, 10])
 def test_deflate_small(dev, tb):
     ch = workloads.deflate_workload(seed=5, total_bytes=48 * 65536)
     _say(f"deflate small tb={tb} chunks={ch.n_chunks}")
