@@ -71,16 +71,19 @@ typedef struct codag_opts {
  *   chunk_offsets  device, n_chunks + 1 non-decreasing uint64: chunk i is
  *                  comp_buf[chunk_offsets[i] .. chunk_offsets[i+1]).  Input
  *                  ranges may overlap.  Loads stay inside the 16-byte-aligned
- *                  hull of each chunk's range.
+ *                  hull of each chunk's range.  A chunk's compressed length
+ *                  is below 2^31 bytes (Deflate: below 2^28), otherwise the
+ *                  chunk fails with CODAG_E_INVALID_ARGUMENT.
  *   out_buf        device, the decompressed bytes.
  *   out_offsets    device, n_chunks + 1 non-decreasing uint64: chunk i
  *                  decodes into out_buf[out_offsets[i] .. out_offsets[i+1]),
- *                  which it must fill exactly.  Output ranges must not
+ *                  which it must fill exactly (below 2^31 bytes).  Output
+ *                  ranges must not
  *                  overlap.  For the RLE codecs each range is a whole number
  *                  of little-endian int64 values and starts 8-byte aligned
  *                  (otherwise the chunk fails with CODAG_E_INVALID_ARGUMENT
  *                  and nothing is written for it).
- *   n_chunks       number of chunks (0 is a no-op).
+ *   n_chunks       number of chunks, below 2^32 - 64 (0 is a no-op).
  *   stream         hipStream_t the work is enqueued on.
  *
  * Returns CODAG_OK once the work is enqueued, CODAG_E_INVALID_ARGUMENT for an

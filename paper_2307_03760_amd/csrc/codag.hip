@@ -39,16 +39,17 @@ __device__ __forceinline__ uint64_t error_key(uint64_t chunk, int st) {
 // Decodes chunk c with the calling wave; returns its status.
 template <int Codec, int TB, uint32_t H>
 __device__ __forceinline__ int decode_one(const uint8_t *comp, const uint64_t *coff, uint8_t *out,
-                                          const uint64_t *ooff, uint64_t c, uint32_t *ring,
+                                          const uint64_t *ooff, uint32_t c, uint32_t *ring,
                                           uint32_t *land, WaveScratch<Codec, TB, H> *scratch) {
     uint64_t i0 = coff[c], i1 = coff[c + 1], o0 = ooff[c], o1 = ooff[c + 1];
-    if (i1 < i0 || o1 < o0 || i1 - i0 >= (1ull << 31) || o1 - o0 >= (1ull << 31))
-        return CODAG_E_INVALID_ARGUMENT;
+    // Decreasing offsets wrap to huge differences: one test covers both.
+    if ((((i1 - i0) | (o1 - o0)) >> 31) != 0) return CODAG_E_INVALID_ARGUMENT;
     uint32_t in_len = (uint32_t)(i1 - i0), out_len = (uint32_t)(o1 - o0);
     uint8_t *dst = out + o0;
     InRing in;
     int st;
     if constexpr (Codec == CODAG_DEFLATE) {
+        if (in_len >= (1u << 28)) return CODAG_E_INVALID_ARGUMENT;  // bit counts fit 31 bits
         in.init(comp + i0, in_len, ring, land);
         st = decode_deflate<TB, H>(in, dst, out_len, &scratch->t);
     } else {
@@ -66,7 +67,7 @@ __device__ __forceinline__ int decode_one(const uint8_t *comp, const uint64_t *c
     return st;
 }
 
-__device__ __forceinline__ void report(uint64_t c, int st, int32_t *status,
+__device__ __forceinline__ void report(uint32_t c, int st, int32_t *status,
                                        unsigned long long *err) {
     if (lane() == 0) {
         if (status) status[c] = st;
@@ -80,12 +81,12 @@ __device__ __forceinline__ void report(uint64_t c, int st, int32_t *status,
 template <int Codec, int TB, uint32_t H, int WPB>
 __global__ void __launch_bounds__(kWave * WPB)
     decode_plain(const uint8_t *comp, const uint64_t *coff, uint8_t *out, const uint64_t *ooff,
-                 uint64_t n, int32_t *status, unsigned long long *err, uint64_t *ticks) {
+                 uint32_t n, int32_t *status, unsigned long long *err, uint64_t *ticks) {
     __shared__ __align__(16) uint32_t s_ring[WPB][kRingLdsWords];
     __shared__ __align__(16) uint32_t s_land[WPB][kLandWords];
     __shared__ __align__(16) WaveScratch<Codec, TB, H> s_scratch[WPB];
     uint32_t wave = uni(threadIdx.x / kWave);
-    uint64_t c = (uint64_t)blockIdx.x * WPB + wave;
+    uint32_t c = blockIdx.x * WPB + wave;
     if (c >= n) return;
     uint64_t t0 = ticks ? __builtin_amdgcn_s_memtime() : 0;
     int st = decode_one<Codec, TB, H>(comp, coff, out, ooff, c, s_ring[wave], s_land[wave],
@@ -138,7 +139,7 @@ int launch_wpb(const uint8_t *comp, const uint64_t *coff, uint8_t *out, const ui
                hipStream_t stream) {
     uint64_t grid = (n + WPB - 1) / WPB;
     hipLaunchKernelGGL((decode_plain<Codec, TB, H, WPB>), dim3((uint32_t)grid), dim3(kWave * WPB),
-                       0, stream, comp, coff, out, ooff, n, status, err, ticks);
+                       0, stream, comp, coff, out, ooff, (uint32_t)n, status, err, ticks);
     return hipGetLastError() == hipSuccess ? CODAG_OK : CODAG_E_HIP;
 }
 
@@ -178,7 +179,7 @@ int codag_decompress_ex(int codec, const uint8_t *comp_buf, const uint64_t *chun
         return CODAG_E_INVALID_ARGUMENT;
     if (n_chunks == 0) return CODAG_OK;
     if (!comp_buf || !chunk_offsets || !out_buf || !out_offsets) return CODAG_E_INVALID_ARGUMENT;
-    if (n_chunks > (1ull << 40)) return CODAG_E_INVALID_ARGUMENT;
+    if (n_chunks >= (1ull << 32) - 64) return CODAG_E_INVALID_ARGUMENT;
     int wpb = opts && opts->waves_per_block ? opts->waves_per_block : 4;
     int tb = opts && opts->lit_table_bits ? opts->lit_table_bits : 10;
     int hist = opts && opts->history_kib ? opts->history_kib : 8;

@@ -180,7 +180,9 @@ struct BitIn {
     uint64_t buf;    // valid bits are the low `cnt`
     uint32_t cnt;
     uint32_t next;   // byte position of the next (aligned) word to load
-    int64_t remain;  // input bits not yet consumed (negative: past the end)
+    int32_t remain;  // input bits not yet consumed (negative: past the end);
+                     // 32 bits because there is no scalar 64-bit ordered
+                     // compare (chunks are below 256 MiB)
 
     __device__ __forceinline__ void seek(InRing &in, uint32_t pos) {
         if (pos >= in.loaded + kFetchBytes) in.restart(pos);
@@ -191,7 +193,7 @@ struct BitIn {
         buf = w >> sh;
         cnt = 32 - sh;
         next = a + 4;
-        remain = 8ll * ((int64_t)in.gend - (int64_t)pos);
+        remain = 8 * ((int32_t)in.gend - (int32_t)pos);
     }
     __device__ __forceinline__ void refill(InRing &in) {
         if (cnt <= 32) {
@@ -206,8 +208,28 @@ struct BitIn {
     __device__ __forceinline__ bool drop(uint32_t n) {
         buf >>= n;
         cnt -= n;
-        remain -= n;
+        remain -= (int32_t)n;
         return remain >= 0;
+    }
+    // Consume n bits without the end-of-input test.  Bits past the end read
+    // as zero; `remain` only decreases, so a decoder that tests it wherever
+    // it stops (an error, the end of a block) reports running past the end
+    // exactly where a bit-by-bit reader would have.
+    __device__ __forceinline__ void skip(uint32_t n) {
+        buf >>= n;
+        cnt -= n;
+        remain -= (int32_t)n;
+    }
+    // Refill with at most one ring advance (the reader moves 4 bytes at a
+    // time, the ring 1 KiB), keeping the hot loop free of inner loops.
+    __device__ __forceinline__ void refill1(InRing &in) {
+        if (cnt <= 32) {
+            if (in.loaded < next + 4) in.commit();
+            uint32_t w = uni(in.word(next >> 2));
+            buf |= (uint64_t)w << cnt;
+            cnt += 32;
+            next += 4;
+        }
     }
     __device__ __forceinline__ uint32_t peek(uint32_t n) const {
         return (uint32_t)(buf & ((1ull << n) - 1));
@@ -232,80 +254,105 @@ __device__ __forceinline__ uint32_t slow_symbol(const BitIn &bi, const CodeMeta 
     return entry16(kInvalid, 0, 0);
 }
 
-// Output through the LDS history window.  Bytes at absolute addresses below
-// `fa` (a multiple of 1 KiB) are in HBM; bytes in [fa, ob + pos) only in the
-// window.  `room` = fa + H - (ob + pos): bytes that can be appended before the
-// oldest unflushed kilobyte must go out.
+// Single-byte LDS writes in the decode loops are issued by all lanes with
+// the same address and value rather than by one lane: a one-lane branch
+// inside a loop that also has early exits makes the compiler treat the loop
+// exit as divergent, which moves the whole bit reader out of scalar
+// registers.
+
+// Output through the LDS history window.  Positions are 32-bit offsets from
+// `base`, the chunk's output address rounded down to 1 KiB (uniform values
+// stay in scalar registers; there are no scalar 64-bit ordered compares).
+// Bytes below `fa` are in HBM; bytes in [fa, o0 + pos) only in the window,
+// where the byte at offset x lives at window[(base + x) % H].
+// `room` = fa + H - (o0 + pos): bytes that can be appended before the oldest
+// unflushed kilobyte must go out.
 template <uint32_t H>
 struct WindowOut {
-    uint8_t *ob;      // the chunk's output range in HBM
-    uint8_t *win;     // the wave's window (H bytes, LDS)
-    uint64_t oabs;    // ob as an integer
-    uint64_t fa;
+    uint8_t *base;  // 1 KiB aligned
+    uint8_t *win;   // the wave's window (H bytes, LDS)
+    uint32_t o0;    // the chunk's first output byte, relative to base (0..1023)
+    uint32_t fa;    // relative, multiple of 1 KiB
     uint32_t cap, pos, room;
 
     __device__ __forceinline__ void init(uint8_t *out, uint32_t capacity, uint8_t *window) {
-        ob = out;
+        // Pointer arithmetic keeps `base` a global pointer: flat stores
+        // would also count against the LDS wait counter.
+        o0 = (uint32_t)(reinterpret_cast<uintptr_t>(out) & 1023);
+        base = out - o0;
         win = window;
-        oabs = reinterpret_cast<uintptr_t>(out);
-        fa = oabs & ~(uint64_t)1023;
+        fa = 0;
         cap = capacity;
         pos = 0;
-        room = (uint32_t)(fa + H - oabs);
+        room = H - o0;
     }
-    __device__ __forceinline__ uint32_t slot(uint64_t a) const { return (uint32_t)a & (H - 1); }
+    // base is 1 KiB aligned and H a power of two >= 1 KiB, so the slot of an
+    // offset does not depend on base.
+    __device__ __forceinline__ uint32_t slot(uint32_t x) const { return x & (H - 1); }
 
     // Writes the kilobyte [fa, fa + 1024) to HBM, restricted to the bytes of
-    // the chunk's range below `limit` (an absolute address).
-    __device__ __forceinline__ void flush_block(uint64_t limit) {
-        uint64_t a = fa + 16 * lane();
+    // the chunk's range below `limit` (relative).
+    __device__ __forceinline__ void flush_block(uint32_t limit) {
+        uint32_t a = fa + 16 * lane();
         uint32_t sl = slot(a);
-        if (a >= oabs && a + 16 <= limit) {
-            *reinterpret_cast<uint4 *>(reinterpret_cast<uint8_t *>(a)) =
-                *reinterpret_cast<const uint4 *>(win + sl);
-        } else if (a + 16 > oabs && a < limit) {
+        if (a >= o0 && a + 16 <= limit) {
+            *reinterpret_cast<uint4 *>(base + a) = *reinterpret_cast<const uint4 *>(win + sl);
+        } else if (a + 16 > o0 && a < limit) {
             for (uint32_t k = 0; k < 16; k++)
-                if (a + k >= oabs && a + k < limit) reinterpret_cast<uint8_t *>(a)[k] = win[sl + k];
+                if (a + k >= o0 && a + k < limit) base[a + k] = win[sl + k];
         }
         fa += 1024;
     }
     __device__ __forceinline__ void make_room(uint32_t len) {
         while (room < len) {
-            flush_block(oabs + cap);
+            flush_block(o0 + cap);
+            room += 1024;
+        }
+    }
+    // As make_room for len <= 258: one flush always suffices.
+    __device__ __forceinline__ void make_room1(uint32_t len) {
+        if (room < len) {
+            flush_block(o0 + cap);
             room += 1024;
         }
     }
     __device__ __forceinline__ void put_literal(uint32_t b) {
-        make_room(1);
-        if (lane() == 0) win[slot(oabs + pos)] = (uint8_t)b;
+        make_room1(1);
+        win[slot(o0 + pos)] = (uint8_t)b;  // same byte from every lane
         pos++;
         room--;
     }
     // Back-reference: len bytes from dist bytes back (dist <= pos).  With
     // len > dist the bytes repeat with period dist.
     __device__ __forceinline__ void copy(uint32_t dist, uint32_t len) {
-        make_room(len);
-        uint64_t dst = oabs + pos;
-        uint64_t lds_from = dst + len - H;  // older bytes may be overwritten below
-        bool near = dist + len <= H;
-        uint32_t r = 0, step = 0;
-        if (dist < len) {
-            r = lane() % dist;
-            step = kWave % dist;
-        }
-        for (uint32_t i = lane(); i < len; i += kWave) {
-            uint64_t q = dst - dist + (dist < len ? r : i);
-            uint8_t b;
-            if (near || q >= lds_from) {
-                b = win[slot(q)];
+        make_room1(len);
+        uint32_t dst = o0 + pos;
+        if (dist + len <= H) {
+            // Every source byte is still in the window and this copy's own
+            // writes only replace bytes older than dist.
+            if (dist >= len) {
+                for (uint32_t i = lane(); i < len; i += kWave) win[slot(dst + i)] = win[slot(dst - dist + i)];
             } else {
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                b = *reinterpret_cast<const uint8_t *>(q);
+                uint32_t r = lane() % dist, step = kWave % dist;
+                for (uint32_t i = lane(); i < len; i += kWave) {
+                    win[slot(dst + i)] = win[slot(dst - dist + r)];
+                    r += step;
+                    if (r >= dist) r -= dist;
+                }
             }
-            win[slot(dst + i)] = b;
-            if (dist < len) {
-                r += step;
-                if (r >= dist) r -= dist;
+        } else {
+            // Far reference (dist > H - len >= len): bytes below dst + len - H
+            // may be overwritten in the window but are already in HBM.
+            int32_t lds_from = (int32_t)(dst + len) - (int32_t)H;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            for (uint32_t i = lane(); i < len; i += kWave) {
+                uint32_t q = dst - dist + i;
+                // Separate loads keep each access in its own address space (a
+                // select between the two pointers would become a flat load).
+                uint8_t g = 0;
+                if ((int32_t)q < lds_from) g = base[q];
+                uint8_t w = win[slot(q)];
+                win[slot(dst + i)] = (int32_t)q >= lds_from ? w : g;
             }
         }
         pos += len;
@@ -313,10 +360,80 @@ struct WindowOut {
     }
     // Writes every byte produced so far to HBM.
     __device__ __forceinline__ void finish() {
-        uint64_t end = oabs + pos;
+        uint32_t end = o0 + pos;
         while (fa < end) flush_block(end);
     }
 };
+
+// Symbols of one Huffman block, up to and including end-of-block.  Returns
+// CODAG_OK at the end of the block or an error status; running past the end
+// of input anywhere before that point is reported as CODAG_E_TRUNCATED.
+// The loop is kept small and with few exits: literals first, then
+// length/distance pairs; everything rare leaves the loop.
+template <int TB, uint32_t H>
+__device__ __forceinline__ int inflate_symbols(InRing &in, BitIn &bi, WindowOut<H> &o,
+                                               DeflateLds<TB, H> *lds, bool have_dist,
+                                               uint32_t len_tab, uint32_t dist_tab) {
+    int st;
+    for (;;) {
+        bi.refill1(in);
+        uint32_t e = uni((uint32_t)lds->lit[bi.peek(TB)]);
+        if (e < (kBase << 13)) {  // literal
+            bi.skip(e & 15);
+            if (o.pos == o.cap) {
+                st = CODAG_E_OVERFLOW;
+                break;
+            }
+            o.put_literal(e >> 4);
+            continue;
+        }
+        if ((e >> 13) == kSlow) e = slow_symbol(bi, &lds->lit_meta, lds->lit_sorted, kLitLen);
+        uint32_t kind = e >> 13;
+        if (kind == kLit) {
+            bi.skip(e & 15);
+            if (o.pos == o.cap) {
+                st = CODAG_E_OVERFLOW;
+                break;
+            }
+            o.put_literal((e >> 4) & 255);
+            continue;
+        }
+        if (kind != kBase) {  // end of block, or an invalid code
+            if (kind != kInvalid) bi.skip(e & 15);
+            st = kind == kEob ? CODAG_OK : CODAG_E_CORRUPT;
+            break;
+        }
+        // Length, then distance.
+        bi.skip(e & 15);
+        uint32_t lb = readlane(len_tab, ((e >> 4) & 511) - 257);
+        uint32_t ex = lb >> 16;
+        uint32_t len = (lb & 0xffff) + bi.peek(ex);
+        bi.skip(ex);
+        bi.refill1(in);
+        uint32_t d = uni((uint32_t)lds->dist[bi.peek(kDistBits)]);
+        if ((d >> 13) == kSlow) d = slow_symbol(bi, &lds->dist_meta, lds->dist_sorted, kDist);
+        if ((d >> 13) != kBase || !have_dist) {
+            if ((d >> 13) == kBadSym && have_dist) bi.skip(d & 15);
+            st = CODAG_E_CORRUPT;
+            break;
+        }
+        bi.skip(d & 15);
+        uint32_t db = readlane(dist_tab, (d >> 4) & 31);
+        uint32_t dex = db >> 16;
+        uint32_t dist = (db & 0xffff) + bi.peek(dex);
+        bi.skip(dex);
+        if (dist > o.pos) {
+            st = CODAG_E_CORRUPT;
+            break;
+        }
+        if (o.pos + len > o.cap) {
+            st = CODAG_E_OVERFLOW;
+            break;
+        }
+        o.copy(dist, len);
+    }
+    return bi.remain < 0 ? CODAG_E_TRUNCATED : st;
+}
 
 template <int TB, uint32_t H>
 __device__ __forceinline__ int decode_deflate(InRing &in, uint8_t *out, uint32_t cap,
@@ -351,7 +468,7 @@ __device__ __forceinline__ int decode_deflate(InRing &in, uint8_t *out, uint32_t
                 uint32_t piece = min(len - done, 512u);
                 o.make_room(piece);
                 in.ensure(p + done + piece + 4);
-                uint64_t dst = o.oabs + o.pos;
+                uint32_t dst = o.o0 + o.pos;
                 for (uint32_t i = l; i < piece; i += kWave) {
                     uint32_t q = p + done + i;
                     o.win[o.slot(dst + i)] = (uint8_t)(in.word(q >> 2) >> (8 * (q & 3)));
@@ -394,7 +511,7 @@ __device__ __forceinline__ int decode_deflate(InRing &in, uint8_t *out, uint32_t
                     bi.refill(in);
                     uint32_t v = bi.peek(3);
                     if (!bi.drop(3)) { trunc = true; break; }
-                    if (l == 0) lds->lens[kCodeLenOrder[i]] = (uint8_t)v;
+                    lds->lens[kCodeLenOrder[i]] = (uint8_t)v;  // same byte from every lane
                 }
                 if (trunc) { st = CODAG_E_TRUNCATED; break; }
                 __builtin_amdgcn_wave_barrier();
@@ -408,7 +525,7 @@ __device__ __forceinline__ int decode_deflate(InRing &in, uint8_t *out, uint32_t
                     uint32_t sym = (e >> 4) & 511;
                     if (!bi.drop(e & 15)) { st = CODAG_E_TRUNCATED; break; }
                     if (sym < 16) {
-                        if (l == 0) lds->lens[idx] = (uint8_t)sym;
+                        lds->lens[idx] = (uint8_t)sym;  // same byte from every lane
                         prev = sym;
                         idx++;
                         continue;
@@ -450,49 +567,7 @@ __device__ __forceinline__ int decode_deflate(InRing &in, uint8_t *out, uint32_t
                 }
                 have_dist = dr.total != 0;
             }
-            // Symbols until end of block.
-            for (;;) {
-                bi.refill(in);
-                uint32_t e = uni((uint32_t)lds->lit[bi.peek(TB)]);
-                uint32_t kind = e >> 13;
-                if (kind == kSlow) {
-                    e = slow_symbol(bi, &lds->lit_meta, lds->lit_sorted, kLitLen);
-                    kind = e >> 13;
-                }
-                if (kind == kInvalid) { st = CODAG_E_CORRUPT; break; }
-                if (!bi.drop(e & 15)) { st = CODAG_E_TRUNCATED; break; }
-                uint32_t sym = (e >> 4) & 511;
-                if (kind == kLit) {
-                    if (o.pos >= cap) { st = CODAG_E_OVERFLOW; break; }
-                    o.put_literal(sym);
-                    continue;
-                }
-                if (kind == kEob) break;
-                if (kind == kBadSym) { st = CODAG_E_CORRUPT; break; }
-                // Length, then distance.
-                uint32_t lb = readlane(len_tab, sym - 257);
-                uint32_t ex = lb >> 16;
-                uint32_t len = (lb & 0xffff) + bi.peek(ex);
-                if (!bi.drop(ex)) { st = CODAG_E_TRUNCATED; break; }
-                if (!have_dist) { st = CODAG_E_CORRUPT; break; }
-                bi.refill(in);
-                uint32_t d = uni((uint32_t)lds->dist[bi.peek(kDistBits)]);
-                uint32_t dk = d >> 13;
-                if (dk == kSlow) {
-                    d = slow_symbol(bi, &lds->dist_meta, lds->dist_sorted, kDist);
-                    dk = d >> 13;
-                }
-                if (dk == kInvalid) { st = CODAG_E_CORRUPT; break; }
-                if (!bi.drop(d & 15)) { st = CODAG_E_TRUNCATED; break; }
-                if (dk == kBadSym) { st = CODAG_E_CORRUPT; break; }
-                uint32_t db = readlane(dist_tab, (d >> 4) & 31);
-                uint32_t dex = db >> 16;
-                uint32_t dist = (db & 0xffff) + bi.peek(dex);
-                if (!bi.drop(dex)) { st = CODAG_E_TRUNCATED; break; }
-                if (dist > o.pos) { st = CODAG_E_CORRUPT; break; }
-                if (o.pos + len > cap) { st = CODAG_E_OVERFLOW; break; }
-                o.copy(dist, len);
-            }
+            st = inflate_symbols<TB, H>(in, bi, o, lds, have_dist, len_tab, dist_tab);
             if (st) break;
         }
         if (last) break;

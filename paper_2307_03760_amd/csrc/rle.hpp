@@ -126,9 +126,9 @@ __device__ __forceinline__ int rle_literal_list(InRing &in, uint32_t &pos, uint3
 
 // Runs: header 0..127 = length - 3, a signed delta byte, a zigzag varint base.
 // Literal lists: header -1..-128 = -count, then count zigzag varints.
-__device__ __forceinline__ int decode_rle_v1(InRing &in, uint64_t *out, uint64_t cap, uint32_t *ends) {
+__device__ __forceinline__ int decode_rle_v1(InRing &in, uint64_t *out, uint32_t cap, uint32_t *ends) {
     uint32_t pos = in.skip, end = in.gend;
-    uint64_t n = 0;
+    uint32_t n = 0;
     while (n < cap) {
         if (pos >= end) return CODAG_E_TRUNCATED;
         in.ensure(pos + 16);
@@ -206,7 +206,7 @@ __device__ __forceinline__ void ensure_packed_batch(InRing &in, uint32_t sec, ui
 // SHORT_REPEAT, past the window, at the end of input or when the output is
 // full, leaving pos at the next unread header.
 __device__ __forceinline__ int rle_v2_short_repeats(InRing &in, uint32_t &pos, uint32_t end,
-                                                    uint64_t *out, uint64_t &n, uint64_t cap) {
+                                                    uint64_t *out, uint32_t &n, uint32_t cap) {
     in.ensure(pos + 80);
     uint64_t lo, hi;
     ring_read16(in, pos + lane(), lo, hi);
@@ -238,9 +238,9 @@ __device__ __forceinline__ int rle_v2_short_repeats(InRing &in, uint32_t &pos, u
     return st;
 }
 
-__device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint64_t cap) {
+__device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t cap) {
     uint32_t pos = in.skip, end = in.gend;
-    uint64_t n = 0;
+    uint32_t n = 0;
     const uint32_t l = lane();
     while (n < cap) {
         if (pos >= end) return CODAG_E_TRUNCATED;
@@ -345,7 +345,7 @@ __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint64_t
                 if (l == 1 && len >= 2) out[n + 1] = base + dbase;
                 uint32_t nd = len >= 2 ? len - 2 : 0, nbytes = (nd * w + 7) >> 3;
                 if (p + nbytes > end) return CODAG_E_TRUNCATED;
-                bool neg = (int64_t)dbase < 0;
+                bool neg = (uint32_t)(dbase >> 63) != 0;
                 uint64_t prev = base + dbase;
                 for (uint32_t i0 = 0; i0 < nd; i0 += kWave) {
                     ensure_packed_batch(in, p, i0, w);

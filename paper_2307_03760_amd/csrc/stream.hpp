@@ -52,9 +52,10 @@ struct InRing {
 
     __device__ __forceinline__ void init(const uint8_t *chunk, uint32_t len, uint32_t *ring_lds,
                                          uint32_t *land_lds) {
-        uintptr_t a = reinterpret_cast<uintptr_t>(chunk);
-        gbase = reinterpret_cast<const uint8_t *>(a & ~(uintptr_t)15);
-        skip = (uint32_t)(a & 15);
+        // Pointer arithmetic (not an integer round trip) keeps the pointer
+        // in the global address space, so loads are global, not flat.
+        skip = (uint32_t)(reinterpret_cast<uintptr_t>(chunk) & 15);
+        gbase = chunk - skip;
         gend = skip + len;
         loaded = 0;
         ring = ring_lds;
