@@ -123,6 +123,168 @@ const char *codag_status_string(int status);
  * re-creates them. */
 void codag_shutdown(void);
 
+
+/* ------------------------------------------------------------------------
+ * Batched launch: many chunks of mixed codecs in one persistent kernel.
+ *
+ * A persistent grid (resident waves on every CU) takes chunk indices from a
+ * device-side work queue; each wave decodes its chunk with the chunk's codec
+ * and takes the next.  The queue order decides how uneven chunks balance
+ * across the CUs.  Output bytes are identical whatever the order.
+ * ------------------------------------------------------------------------ */
+
+/* Queue orders. */
+enum {
+    CODAG_ORDER_INDEX = 0,   /* chunk index order (plain atomic queue) */
+    CODAG_ORDER_GIVEN = 1,   /* the caller's permutation (`order` argument) */
+    CODAG_ORDER_LEARNED = 2  /* longest predicted decode time first, predicted by
+                                the plan's cost model (see codag_sched_*); a
+                                plan whose model was never trained or set runs
+                                in index order */
+};
+
+/*
+ * Launch configuration of a plan; zero fields select defaults.
+ *   waves_per_cu      resident waves per CU in the persistent grid (default:
+ *                     as many as the per-wave LDS allows, at most 16).
+ *   waves_per_block   1, 2 or 4 (default 2).
+ *   lit_table_bits    Deflate literal/length table bits; only 10 here.
+ *   history_kib       Deflate LDS history window, 8 or 16 KiB (default 8).
+ *   order             CODAG_ORDER_* (default CODAG_ORDER_INDEX).
+ *   use_graph         nonzero: capture the launch sequence (queue reset,
+ *                     scheduling steps, decode) in a hipGraph once per set of
+ *                     arguments and replay it.
+ */
+typedef struct codag_batch_opts {
+    int waves_per_cu;
+    int waves_per_block;
+    int lit_table_bits;
+    int history_kib;
+    int order;
+    int use_graph;
+    int reserved[10];
+} codag_batch_opts;
+
+typedef struct codag_plan codag_plan;
+
+/* Create a plan on the current device (its device buffers are allocated
+ * here and grown on demand by later calls).  opts may be NULL. */
+int codag_plan_create(codag_plan **plan, const codag_batch_opts *opts);
+/* Synchronize the plan's work and release it. */
+void codag_plan_destroy(codag_plan *plan);
+/* Read or replace the plan's launch configuration (replacing drops any
+ * captured graph). */
+int codag_plan_get_opts(const codag_plan *plan, codag_batch_opts *opts);
+int codag_plan_set_opts(codag_plan *plan, const codag_batch_opts *opts);
+
+/*
+ * Decompress n_chunks chunks whose codecs are codecs[i] (device, uint8,
+ * CODAG_RLE_V1/V2/DEFLATE; anything else fails that chunk with
+ * CODAG_E_INVALID_ARGUMENT).  Buffers, offsets and output rules are those of
+ * codag_decompress.
+ *   chunk_status  device, n_chunks int32, may be NULL.
+ *   order         device, n_chunks uint32 permutation of 0..n_chunks-1, used
+ *                 with CODAG_ORDER_GIVEN (ignored otherwise).  An entry
+ *                 >= n_chunks is skipped and recorded as an
+ *                 CODAG_E_INVALID_ARGUMENT error (codag_get_error) naming
+ *                 its queue position; with repeated entries some chunks are
+ *                 decoded twice and others not at all.
+ *   chunk_ticks   device, n_chunks uint64, may be NULL: each chunk's decode
+ *                 time in shader clock cycles.
+ * Enqueued on `stream`; returns CODAG_E_INVALID_ARGUMENT for bad arguments,
+ * CODAG_E_HIP if a launch or graph operation fails.  Calls that share a plan
+ * must not overlap in time (they share its queue).
+ */
+int codag_decompress_batch(codag_plan *plan, const uint8_t *codecs, const uint8_t *comp_buf,
+                           const uint64_t *chunk_offsets, uint8_t *out_buf,
+                           const uint64_t *out_offsets, uint64_t n_chunks,
+                           int32_t *chunk_status, const uint32_t *order,
+                           uint64_t *chunk_ticks, void *stream);
+
+/*
+ * Time candidate launch configurations on these buffers (each `reps` times,
+ * on `stream`, which is synchronized) and keep the fastest in the plan.
+ * *best_ms (may be NULL) receives its time per launch.  The buffers are
+ * decoded many times; the output is the same each time.
+ */
+int codag_autotune(codag_plan *plan, const uint8_t *codecs, const uint8_t *comp_buf,
+                   const uint64_t *chunk_offsets, uint8_t *out_buf, const uint64_t *out_offsets,
+                   uint64_t n_chunks, const uint32_t *order, int reps, double *best_ms,
+                   void *stream);
+
+/* ------------------------------------------------------------------------
+ * Learned scheduling: a per-plan cost model.
+ *
+ * The model predicts log2 of a chunk's decode time (shader clock cycles, as
+ * codag_decompress_batch reports them) from 16 features that a header-only
+ * pre-pass reads from each chunk:
+ *   0 log2(1 + compressed bytes)   1 log2(1 + output bytes)   2 = 1 - 0
+ *   3..5  codec one-hot (RLE v1, RLE v2, Deflate)
+ *   6..8  BTYPE one-hot of the first Deflate block (stored, fixed, dynamic)
+ *   9 HLIT/286  10 HDIST/30  11 HCLEN/19 of a dynamic first block
+ *   12..15 shares of that block's literal/length code lengths in
+ *          1-6, 7-8, 9-10 and 11-15 bits
+ * (Deflate header fields as in RFC 1951 section 3.2.7; zero where absent.)
+ *
+ * Network: x' = (x - mu) * s per feature; h1 = relu(W1 x' + b1),
+ * h2 = relu(W2 h1 + b2), y = w3 . h2 + b3 (16-64-64-1, FP32); prediction =
+ * y * sy + my.  Parameters are packed as W1[64][16], b1[64], W2[64][64],
+ * b2[64], w3[64], b3 (CODAG_SCHED_PARAMS floats, row-major, W[out][in]);
+ * normalization as mu[16], s[16], my, sy (CODAG_SCHED_NORM floats).
+ * Loss: mean over samples of (y - (t - my) / sy)^2 for targets t.
+ * All feat/target/pred buffers are device memory; features are n x 16
+ * row-major floats.  Calls are enqueued on `stream` and synchronize it where
+ * they return host values.  Like codag_decompress_batch, calls that share a
+ * plan must not overlap in time.
+ * ------------------------------------------------------------------------ */
+
+#define CODAG_SCHED_FEATURES 16
+#define CODAG_SCHED_PARAMS 5313
+#define CODAG_SCHED_NORM 34
+
+/* Features of n chunks (arguments as codag_decompress_batch) into feat. */
+int codag_sched_features(codag_plan *plan, const uint8_t *codecs, const uint8_t *comp_buf,
+                         const uint64_t *chunk_offsets, const uint64_t *out_offsets,
+                         uint64_t n_chunks, float *feat, void *stream);
+
+/* Replace the model: params (CODAG_SCHED_PARAMS floats) and norm
+ * (CODAG_SCHED_NORM floats) are host arrays.  Marks the model trained. */
+int codag_sched_set_params(codag_plan *plan, const float *params, const float *norm);
+/* Copy the model out (either pointer may be NULL).  Returns
+ * CODAG_E_INVALID_ARGUMENT if the plan has no model yet. */
+int codag_sched_get_params(const codag_plan *plan, float *params, float *norm);
+
+/*
+ * Fit the model to n samples: when seed is nonzero, first re-initialize the
+ * weights (uniform in +-sqrt(6/fan_in), biases zero, from the given seed) and
+ * the normalization (feature and target means and standard deviations of
+ * these samples; a constant feature gets scale 0).  Then take `steps`
+ * full-batch Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr,
+ * moments reset at the start of the call).  losses (host, may be NULL)
+ * receives the loss before each step.  Deterministic for given inputs.
+ * n must be at least 2 and below 2^24.
+ */
+int codag_sched_train(codag_plan *plan, const float *feat, const float *target, uint64_t n,
+                      int steps, float lr, uint64_t seed, float *losses, void *stream);
+
+/* Loss and its gradient with respect to the packed parameters (host grad of
+ * CODAG_SCHED_PARAMS floats, may be NULL; host loss, may be NULL) at the
+ * current model, for n samples. */
+int codag_sched_grad(codag_plan *plan, const float *feat, const float *target, uint64_t n,
+                     float *grad, float *loss, void *stream);
+
+/* Predicted log2 decode cycles of n feature rows into pred (device). */
+int codag_sched_predict(codag_plan *plan, const float *feat, uint64_t n, float *pred,
+                        void *stream);
+
+/* The queue order CODAG_ORDER_LEARNED uses for these chunks, into order
+ * (device, n_chunks uint32): features, prediction, and a descending counting
+ * sort of the prediction over 4096 buckets spanning my +- 4 sy (ties in any
+ * order). */
+int codag_sched_order(codag_plan *plan, const uint8_t *codecs, const uint8_t *comp_buf,
+                      const uint64_t *chunk_offsets, const uint64_t *out_offsets,
+                      uint64_t n_chunks, uint32_t *order, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,6 +15,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcodag.so")
 
 RLE_V1, RLE_V2, DEFLATE = 1, 2, 3
+ORDER_INDEX, ORDER_GIVEN, ORDER_LEARNED = 0, 1, 2
+SCHED_FEATURES, SCHED_PARAMS, SCHED_NORM = 16, 5313, 34
 OK = 0
 E_INVALID_ARGUMENT, E_HIP, E_CORRUPT, E_TRUNCATED, E_OVERFLOW, E_UNDERFLOW = -1, -2, -3, -4, -5, -6
 
@@ -32,6 +34,13 @@ class Opts(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_int), ("lit_table_bits", ctypes.c_int),
                 ("chunk_ticks", ctypes.c_void_p), ("history_kib", ctypes.c_int),
                 ("reserved", ctypes.c_int * 7)]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("waves_per_cu", ctypes.c_int), ("waves_per_block", ctypes.c_int),
+                ("lit_table_bits", ctypes.c_int), ("history_kib", ctypes.c_int),
+                ("order", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("reserved", ctypes.c_int * 10)]
 
 
 def lib():
@@ -53,6 +62,28 @@ def lib():
             L.codag_status_string.restype = ctypes.c_char_p
             L.codag_shutdown.argtypes = []
             L.codag_shutdown.restype = None
+            bo = ctypes.POINTER(BatchOpts)
+            fp, dp = ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)
+            sigs = {
+                "codag_plan_create": [ctypes.POINTER(vp), bo],
+                "codag_plan_get_opts": [vp, bo],
+                "codag_plan_set_opts": [vp, bo],
+                "codag_decompress_batch": [vp, vp, vp, vp, vp, vp, u64, vp, vp, vp, vp],
+                "codag_autotune": [vp, vp, vp, vp, vp, vp, u64, vp, i32, dp, vp],
+                "codag_sched_features": [vp, vp, vp, vp, vp, u64, vp, vp],
+                "codag_sched_set_params": [vp, fp, fp],
+                "codag_sched_get_params": [vp, fp, fp],
+                "codag_sched_train": [vp, vp, vp, u64, i32, ctypes.c_float, u64, fp, vp],
+                "codag_sched_grad": [vp, vp, vp, u64, fp, fp, vp],
+                "codag_sched_predict": [vp, vp, u64, vp, vp],
+                "codag_sched_order": [vp, vp, vp, vp, vp, u64, vp, vp],
+            }
+            for name, args in sigs.items():
+                fn = getattr(L, name)
+                fn.argtypes = args
+                fn.restype = i32
+            L.codag_plan_destroy.argtypes = [vp]
+            L.codag_plan_destroy.restype = None
             _lib = L
     return _lib
 
@@ -121,3 +152,161 @@ def get_error(stream=None):
 
 def shutdown() -> None:
     lib().codag_shutdown()
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise CodagError(rc, what)
+
+
+def _offsets_dtypes():
+    import torch
+    return (torch.int64, torch.uint64) if hasattr(torch, "uint64") else (torch.int64,)
+
+
+def _floats(n, values=None):
+    arr = (ctypes.c_float * n)()
+    if values is not None:
+        import numpy as np
+        v = np.ascontiguousarray(np.asarray(values, dtype=np.float32).reshape(-1))
+        if v.size != n:
+            raise ValueError(f"expected {n} floats, got {v.size}")
+        ctypes.memmove(arr, v.ctypes.data, 4 * n)
+    return arr
+
+
+class Plan:
+    """A batched-launch plan (codag_plan_*) on the current device.
+
+    Holds the persistent kernel's queue, a captured graph per argument set and
+    the learned cost model.  Calls on one plan must not overlap in time.
+    """
+
+    def __init__(self, *, waves_per_cu: int = 0, waves_per_block: int = 0,
+                 history_kib: int = 0, order: int = ORDER_INDEX, use_graph: bool = False):
+        self._h = ctypes.c_void_p()
+        o = BatchOpts(waves_per_cu, waves_per_block, 0, history_kib, order, int(use_graph))
+        _check(lib().codag_plan_create(ctypes.byref(self._h), ctypes.byref(o)), "codag_plan_create")
+
+    def close(self) -> None:
+        if self._h:
+            lib().codag_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def opts(self) -> dict:
+        o = BatchOpts()
+        _check(lib().codag_plan_get_opts(self._h, ctypes.byref(o)), "codag_plan_get_opts")
+        return {k: getattr(o, k) for k, _ in BatchOpts._fields_ if k != "reserved"}
+
+    def set_opts(self, **kw) -> None:
+        cur = self.opts
+        cur.update(kw)
+        o = BatchOpts(*(int(cur[k]) for k, _ in BatchOpts._fields_ if k != "reserved"))
+        _check(lib().codag_plan_set_opts(self._h, ctypes.byref(o)), "codag_plan_set_opts")
+
+    def _args(self, codecs, comp, chunk_offsets, out, out_offsets):
+        import torch
+        n = chunk_offsets.numel() - 1
+        if n < 0 or out_offsets.numel() != n + 1:
+            raise ValueError("offset arrays must hold n_chunks + 1 entries")
+        offs = _offsets_dtypes()
+        return n, [_check_dev(codecs, "codecs", (torch.uint8,), n),
+                   _check_dev(comp, "comp", (torch.uint8,)),
+                   _check_dev(chunk_offsets, "chunk_offsets", offs),
+                   _check_dev(out, "out", (torch.uint8,)) if out is not None else None,
+                   _check_dev(out_offsets, "out_offsets", offs)]
+
+    def decompress(self, codecs, comp, chunk_offsets, out, out_offsets, *, status=None,
+                   order=None, chunk_ticks=None, stream=None) -> None:
+        """Enqueue codag_decompress_batch; tensors as in decompress(), plus
+        codecs (uint8, n), order (int32 permutation, n) and chunk_ticks (int64, n)."""
+        import torch
+        n, (a, b, c, d, e) = self._args(codecs, comp, chunk_offsets, out, out_offsets)
+        st = _check_dev(status, "status", (torch.int32,), n)
+        od = _check_dev(order, "order", (torch.int32,), n)
+        tk = _check_dev(chunk_ticks, "chunk_ticks", (torch.int64,), n)
+        _check(lib().codag_decompress_batch(self._h, a, b, c, d, e, n, st, od, tk,
+                                            _stream_handle(stream)), "codag_decompress_batch")
+
+    def autotune(self, codecs, comp, chunk_offsets, out, out_offsets, *, order=None,
+                 reps: int = 3, stream=None) -> float:
+        """Run codag_autotune; returns the best time per launch in ms."""
+        import torch
+        n, (a, b, c, d, e) = self._args(codecs, comp, chunk_offsets, out, out_offsets)
+        od = _check_dev(order, "order", (torch.int32,), n)
+        best = ctypes.c_double(0)
+        _check(lib().codag_autotune(self._h, a, b, c, d, e, n, od, int(reps), ctypes.byref(best),
+                                    _stream_handle(stream)), "codag_autotune")
+        return best.value
+
+    # -- cost model -------------------------------------------------------
+
+    def features(self, codecs, comp, chunk_offsets, out_offsets, *, stream=None):
+        """n x 16 float32 device tensor of header features."""
+        import torch
+        n, (a, b, c, _, e) = self._args(codecs, comp, chunk_offsets, None, out_offsets)
+        feat = torch.empty((n, SCHED_FEATURES), dtype=torch.float32, device=comp.device)
+        _check(lib().codag_sched_features(self._h, a, b, c, e, n, ctypes.c_void_p(feat.data_ptr()),
+                                          _stream_handle(stream)), "codag_sched_features")
+        return feat
+
+    def set_params(self, params, norm) -> None:
+        _check(lib().codag_sched_set_params(self._h, _floats(SCHED_PARAMS, params),
+                                            _floats(SCHED_NORM, norm)), "codag_sched_set_params")
+
+    def get_params(self):
+        import numpy as np
+        p, q = _floats(SCHED_PARAMS), _floats(SCHED_NORM)
+        _check(lib().codag_sched_get_params(self._h, p, q), "codag_sched_get_params")
+        return np.ctypeslib.as_array(p).copy(), np.ctypeslib.as_array(q).copy()
+
+    def _feat_target(self, feat, target):
+        import torch
+        n = feat.shape[0]
+        if feat.dim() != 2 or feat.shape[1] != SCHED_FEATURES:
+            raise ValueError("feat must be n x 16")
+        return n, _check_dev(feat, "feat", (torch.float32,)), \
+            _check_dev(target, "target", (torch.float32,), n)
+
+    def train(self, feat, target, *, steps: int, lr: float = 1e-3, seed: int = 0, stream=None):
+        """codag_sched_train; returns the loss before each step (numpy)."""
+        import numpy as np
+        n, f, t = self._feat_target(feat, target)
+        losses = _floats(max(steps, 1))
+        _check(lib().codag_sched_train(self._h, f, t, n, int(steps), float(lr), int(seed), losses,
+                                       _stream_handle(stream)), "codag_sched_train")
+        return np.ctypeslib.as_array(losses)[:steps].copy()
+
+    def grad(self, feat, target, *, stream=None):
+        """(loss, gradient over the packed parameters) at the current model."""
+        import numpy as np
+        n, f, t = self._feat_target(feat, target)
+        g, l = _floats(SCHED_PARAMS), _floats(1)
+        _check(lib().codag_sched_grad(self._h, f, t, n, g, l, _stream_handle(stream)),
+               "codag_sched_grad")
+        return float(l[0]), np.ctypeslib.as_array(g).copy()
+
+    def predict(self, feat, *, stream=None):
+        import torch
+        n = feat.shape[0]
+        pred = torch.empty(n, dtype=torch.float32, device=feat.device)
+        _check(lib().codag_sched_predict(self._h, _check_dev(feat, "feat", (torch.float32,)), n,
+                                         ctypes.c_void_p(pred.data_ptr()), _stream_handle(stream)),
+               "codag_sched_predict")
+        return pred
+
+    def order(self, codecs, comp, chunk_offsets, out_offsets, *, stream=None):
+        """The learned queue order (int32 device tensor)."""
+        import torch
+        n, (a, b, c, _, e) = self._args(codecs, comp, chunk_offsets, None, out_offsets)
+        order = torch.empty(n, dtype=torch.int32, device=comp.device)
+        _check(lib().codag_sched_order(self._h, a, b, c, e, n, ctypes.c_void_p(order.data_ptr()),
+                                       _stream_handle(stream)), "codag_sched_order")
+        return order

@@ -1,0 +1,363 @@
+// Batched launch: thousands of mixed-codec chunks in one persistent kernel.
+//
+// The grid holds a fixed number of resident waves per CU; each wave takes
+// the next position of a device-side work queue (one atomic add per chunk),
+// maps it through an optional order array, and decodes that chunk with the
+// chunk's codec using the same per-wave decoders as the plain launch.  The
+// queue order is the scheduler's lever: with chunks of very uneven cost, the
+// order decides how much idle time the last waves leave at the end.  The
+// sequence (queue reset, optional scheduling kernels, decode) can be captured
+// once in a hipGraph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/codag.h"
+#include "decode.hpp"
+#include "internal.hpp"
+#include "sched.hpp"
+
+namespace codag {
+
+__global__ void reset_queue(uint32_t *head) {
+    if (threadIdx.x == 0) *head = 0;
+}
+
+// One wave per queue position until the queue is empty.  Every store of a
+// per-chunk result is made by all lanes with the same value (a one-lane
+// branch inside this loop would make the compiler treat the loop as
+// divergent).
+template <int TB, uint32_t H, int WPB>
+__global__ void __launch_bounds__(kWave * WPB)
+    decode_batch(const uint8_t *codecs, const uint8_t *comp, const uint64_t *coff, uint8_t *out,
+                 const uint64_t *ooff, uint32_t n, const uint32_t *order, uint32_t *head,
+                 int32_t *status, unsigned long long *err, uint64_t *ticks) {
+    __shared__ __align__(16) uint32_t s_ring[WPB][kRingLdsWords];
+    __shared__ __align__(16) uint32_t s_land[WPB][kLandWords];
+    __shared__ __align__(16) WaveScratch<CODAG_DEFLATE, TB, H> s_scratch[WPB];
+    const uint32_t wave = uni(threadIdx.x / kWave);
+    for (;;) {
+        // Lane 0 adds one; the others add zero, so lane 0's old value is the
+        // claimed position whatever order the lanes' adds are applied in.
+        uint32_t idx = uni(atomicAdd(head, lane() == 0 ? 1u : 0u));
+        if (idx >= n) break;
+        uint32_t c = order ? uni(order[idx]) : idx;
+        if (c >= n) {  // not a permutation: report the queue position
+            atomicMin(err, (unsigned long long)error_key(idx, CODAG_E_INVALID_ARGUMENT));
+            continue;
+        }
+        uint32_t codec = uni((uint32_t)codecs[c]);
+        uint64_t t0 = __builtin_amdgcn_s_memtime();
+        int st;
+        if (codec == CODAG_RLE_V1)
+            st = decode_one<CODAG_RLE_V1, TB, H>(
+                comp, coff, out, ooff, c, s_ring[wave], s_land[wave],
+                reinterpret_cast<WaveScratch<CODAG_RLE_V1, TB, H> *>(&s_scratch[wave]));
+        else if (codec == CODAG_RLE_V2)
+            st = decode_one<CODAG_RLE_V2, TB, H>(
+                comp, coff, out, ooff, c, s_ring[wave], s_land[wave],
+                reinterpret_cast<WaveScratch<CODAG_RLE_V2, TB, H> *>(&s_scratch[wave]));
+        else if (codec == CODAG_DEFLATE)
+            st = decode_one<CODAG_DEFLATE, TB, H>(comp, coff, out, ooff, c, s_ring[wave],
+                                                  s_land[wave], &s_scratch[wave]);
+        else
+            st = CODAG_E_INVALID_ARGUMENT;
+        uint64_t t1 = __builtin_amdgcn_s_memtime();
+        if (ticks) ticks[c] = t1 - t0;
+        if (status) status[c] = st;
+        if (st != CODAG_OK) atomicMin(err, (unsigned long long)error_key(c, st));
+    }
+}
+
+template <int TB, uint32_t H>
+constexpr uint32_t batch_lds_per_wave() {
+    return (uint32_t)(4 * kRingLdsWords + 4 * kLandWords + sizeof(WaveScratch<CODAG_DEFLATE, TB, H>));
+}
+
+}  // namespace codag
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+using namespace codag;
+
+namespace {
+
+constexpr uint32_t kLdsPerCu = 160 * 1024;
+constexpr int kVgprWavesPerSimd = 5;  // the decoders use up to 92 VGPRs
+
+
+uint32_t lds_per_wave(int hist_kib) {
+    return hist_kib == 16 ? batch_lds_per_wave<10, 16384>() : batch_lds_per_wave<10, 8192>();
+}
+
+int max_waves_per_cu(int hist_kib, int wpb) {
+    int by_lds = (int)(kLdsPerCu / (lds_per_wave(hist_kib) * wpb)) * wpb;
+    return std::max(wpb, std::min({by_lds, 4 * kVgprWavesPerSimd, 16}));
+}
+
+}  // namespace
+
+namespace {
+
+void drop_graph(codag_plan *p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+    p->have_key = false;
+}
+
+int resolve_opts(const codag_batch_opts *in, codag_batch_opts *o) {
+    codag_batch_opts r{};
+    if (in) r = *in;
+    if (r.waves_per_block == 0) r.waves_per_block = 2;
+    if (r.lit_table_bits == 0) r.lit_table_bits = 10;
+    if (r.history_kib == 0) r.history_kib = 8;
+    if (r.waves_per_block != 1 && r.waves_per_block != 2 && r.waves_per_block != 4)
+        return CODAG_E_INVALID_ARGUMENT;
+    if (r.lit_table_bits != 10) return CODAG_E_INVALID_ARGUMENT;
+    if (r.history_kib != 8 && r.history_kib != 16) return CODAG_E_INVALID_ARGUMENT;
+    if (r.order < CODAG_ORDER_INDEX || r.order > CODAG_ORDER_LEARNED) return CODAG_E_INVALID_ARGUMENT;
+    if (r.waves_per_cu < 0 || r.waves_per_cu > 64) return CODAG_E_INVALID_ARGUMENT;
+    if (r.waves_per_cu == 0) r.waves_per_cu = max_waves_per_cu(r.history_kib, r.waves_per_block);
+    *o = r;
+    return CODAG_OK;
+}
+
+template <uint32_t H, int WPB>
+void launch_decode(codag_plan *p, const BatchArgs &a, const uint32_t *order, unsigned long long *err,
+                   hipStream_t s) {
+    uint32_t blocks = (uint32_t)std::max<int64_t>(1, ((int64_t)p->num_cus * p->opts.waves_per_cu) / WPB);
+    hipLaunchKernelGGL((decode_batch<10, H, WPB>), dim3(blocks), dim3(kWave * WPB), 0, s, a.codecs,
+                       a.comp, a.coff, a.out, a.ooff, (uint32_t)a.n, order, p->head, a.status, err,
+                       a.ticks);
+}
+
+// Enqueue the whole sequence on s.
+int enqueue(codag_plan *p, const BatchArgs &a, unsigned long long *err, hipStream_t s) {
+    hipLaunchKernelGGL(reset_queue, dim3(1), dim3(kWave), 0, s, p->head);
+    const uint32_t *order = nullptr;
+    if (p->opts.order == CODAG_ORDER_GIVEN) {
+        order = a.order;
+    } else if (p->opts.order == CODAG_ORDER_LEARNED && p->sched.trained) {
+        int st = sched_enqueue_order(&p->sched, a.codecs, a.comp, a.coff, a.ooff, (uint32_t)a.n,
+                                     p->sched.order, s);
+        if (st) return st;
+        order = p->sched.order;
+    }
+    bool big = p->opts.history_kib == 16;
+    switch (p->opts.waves_per_block) {
+        case 1:
+            big ? launch_decode<16384, 1>(p, a, order, err, s) : launch_decode<8192, 1>(p, a, order, err, s);
+            break;
+        case 4:
+            big ? launch_decode<16384, 4>(p, a, order, err, s) : launch_decode<8192, 4>(p, a, order, err, s);
+            break;
+        default:
+            big ? launch_decode<16384, 2>(p, a, order, err, s) : launch_decode<8192, 2>(p, a, order, err, s);
+    }
+    return hipGetLastError() == hipSuccess ? CODAG_OK : CODAG_E_HIP;
+}
+
+int run_batch(codag_plan *p, const BatchArgs &a, hipStream_t s) {
+    DeviceState *ds = nullptr;
+    int st = device_state(&ds);
+    if (st) return st;
+    // The scheduler's per-chunk buffers are sized here, never during capture.
+    if (p->opts.order == CODAG_ORDER_LEARNED && p->sched.trained &&
+        (st = sched_reserve(&p->sched, (uint32_t)a.n)))
+        return st;
+    if (!p->opts.use_graph) return enqueue(p, a, ds->err, s);
+    if (!(p->have_key && p->key == a)) {
+        drop_graph(p);
+        if (hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return CODAG_E_HIP;
+        st = enqueue(p, a, ds->err, p->capture);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(p->capture, &g);
+        if (st || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return st ? st : CODAG_E_HIP;
+        }
+        p->graph = g;
+        if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            drop_graph(p);
+            return CODAG_E_HIP;
+        }
+        p->key = a;
+        p->have_key = true;
+    }
+    return hipGraphLaunch(p->exec, s) == hipSuccess ? CODAG_OK : CODAG_E_HIP;
+}
+
+int check_args(codag_plan *plan, const uint8_t *codecs, const uint8_t *comp, const uint64_t *coff,
+               uint8_t *out, const uint64_t *ooff, uint64_t n, const uint32_t *order) {
+    if (!plan) return CODAG_E_INVALID_ARGUMENT;
+    if (n == 0) return CODAG_OK;
+    if (n >= (1ull << 32) - 64) return CODAG_E_INVALID_ARGUMENT;
+    if (!codecs || !comp || !coff || !out || !ooff) return CODAG_E_INVALID_ARGUMENT;
+    if (plan->opts.order == CODAG_ORDER_GIVEN && !order) return CODAG_E_INVALID_ARGUMENT;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return CODAG_E_HIP;
+    if (dev != plan->device) return CODAG_E_INVALID_ARGUMENT;
+    return CODAG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int codag_plan_create(codag_plan **plan, const codag_batch_opts *opts) {
+    if (!plan) return CODAG_E_INVALID_ARGUMENT;
+    *plan = nullptr;
+    auto *p = new codag_plan();
+    if (hipGetDevice(&p->device) != hipSuccess ||
+        hipDeviceGetAttribute(&p->num_cus, hipDeviceAttributeMultiprocessorCount, p->device) !=
+            hipSuccess) {
+        delete p;
+        return CODAG_E_HIP;
+    }
+    int st = resolve_opts(opts, &p->opts);
+    if (st) {
+        delete p;
+        return st;
+    }
+    if (hipMalloc(&p->head, sizeof(uint32_t)) != hipSuccess ||
+        hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking) != hipSuccess) {
+        codag_plan_destroy(p);
+        return CODAG_E_HIP;
+    }
+    st = sched_init(&p->sched);
+    if (st) {
+        codag_plan_destroy(p);
+        return st;
+    }
+    *plan = p;
+    return CODAG_OK;
+}
+
+void codag_plan_destroy(codag_plan *plan) {
+    if (!plan) return;
+    (void)hipDeviceSynchronize();
+    drop_graph(plan);
+    sched_free(&plan->sched);
+    if (plan->head) (void)hipFree(plan->head);
+    if (plan->capture) (void)hipStreamDestroy(plan->capture);
+    delete plan;
+}
+
+int codag_plan_get_opts(const codag_plan *plan, codag_batch_opts *opts) {
+    if (!plan || !opts) return CODAG_E_INVALID_ARGUMENT;
+    *opts = plan->opts;
+    return CODAG_OK;
+}
+
+int codag_plan_set_opts(codag_plan *plan, const codag_batch_opts *opts) {
+    if (!plan) return CODAG_E_INVALID_ARGUMENT;
+    std::lock_guard<std::mutex> lock(plan->mu);
+    codag_batch_opts r;
+    int st = resolve_opts(opts, &r);
+    if (st) return st;
+    plan->opts = r;
+    drop_graph(plan);
+    return CODAG_OK;
+}
+
+int codag_decompress_batch(codag_plan *plan, const uint8_t *codecs, const uint8_t *comp_buf,
+                           const uint64_t *chunk_offsets, uint8_t *out_buf,
+                           const uint64_t *out_offsets, uint64_t n_chunks,
+                           int32_t *chunk_status, const uint32_t *order,
+                           uint64_t *chunk_ticks, void *stream) {
+    int st = check_args(plan, codecs, comp_buf, chunk_offsets, out_buf, out_offsets, n_chunks, order);
+    if (st || n_chunks == 0) return st;
+    std::lock_guard<std::mutex> lock(plan->mu);
+    BatchArgs a{codecs, comp_buf, chunk_offsets, out_buf, out_offsets, n_chunks,
+                chunk_status, plan->opts.order == CODAG_ORDER_GIVEN ? order : nullptr, chunk_ticks};
+    return run_batch(plan, a, static_cast<hipStream_t>(stream));
+}
+
+int codag_autotune(codag_plan *plan, const uint8_t *codecs, const uint8_t *comp_buf,
+                   const uint64_t *chunk_offsets, uint8_t *out_buf, const uint64_t *out_offsets,
+                   uint64_t n_chunks, const uint32_t *order, int reps, double *best_ms,
+                   void *stream) {
+    int st = check_args(plan, codecs, comp_buf, chunk_offsets, out_buf, out_offsets, n_chunks, order);
+    if (st) return st;
+    if (reps < 1 || reps > 1000) return CODAG_E_INVALID_ARGUMENT;
+    std::lock_guard<std::mutex> lock(plan->mu);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const codag_batch_opts base = plan->opts;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return CODAG_E_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return CODAG_E_HIP;
+    }
+    BatchArgs a{codecs, comp_buf, chunk_offsets, out_buf, out_offsets, n_chunks, nullptr,
+                base.order == CODAG_ORDER_GIVEN ? order : nullptr, nullptr};
+    double best = 1e30;
+    codag_batch_opts best_opts = base;
+    auto trial = [&](codag_batch_opts o) -> int {
+        codag_batch_opts r;
+        if (resolve_opts(&o, &r)) return CODAG_OK;
+        plan->opts = r;
+        plan->opts.use_graph = 0;
+        int rc = run_batch(plan, a, s);  // warm-up
+        if (rc) return rc;
+        std::vector<float> t;
+        for (int k = 0; k < reps; k++) {
+            if (hipEventRecord(e0, s) != hipSuccess) return CODAG_E_HIP;
+            rc = run_batch(plan, a, s);
+            if (rc) return rc;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                return CODAG_E_HIP;
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return CODAG_E_HIP;
+            t.push_back(ms);
+        }
+        std::sort(t.begin(), t.end());
+        double med = t[t.size() / 2];
+        if (med < best) {
+            best = med;
+            best_opts = r;
+            best_opts.use_graph = base.use_graph;
+        }
+        return CODAG_OK;
+    };
+    // Coordinate search: window size, then waves per workgroup, then the
+    // number of resident waves per CU.
+    for (int hist : {8, 16}) {
+        codag_batch_opts o = base;
+        o.history_kib = hist;
+        o.waves_per_cu = 0;
+        if ((st = trial(o))) break;
+    }
+    for (int wpb : {1, 2, 4}) {
+        if (st) break;
+        codag_batch_opts o = best_opts;
+        o.waves_per_block = wpb;
+        o.waves_per_cu = 0;
+        st = trial(o);
+    }
+    if (!st) {
+        int top = max_waves_per_cu(best_opts.history_kib, best_opts.waves_per_block);
+        for (int w = top - 2 * best_opts.waves_per_block; w >= std::max(4, top / 2) && !st;
+             w -= 2 * best_opts.waves_per_block) {
+            codag_batch_opts o = best_opts;
+            o.waves_per_cu = w;
+            st = trial(o);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    plan->opts = best_opts;
+    drop_graph(plan);
+    if (best_ms) *best_ms = best;
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,69 @@
+// Per-chunk decoding shared by the plain and the batched launches.
+#pragma once
+
+#include "../../include/codag.h"
+#include "deflate.hpp"
+#include "rle.hpp"
+
+namespace codag {
+
+// Per-wave LDS beyond the input ring and its landing buffer.
+// For Deflate, TB is the literal/length table bits and H the history
+// window bytes.
+template <int Codec, int TB, uint32_t H>
+struct WaveScratch {
+    uint32_t unused;
+};
+template <int TB, uint32_t H>
+struct WaveScratch<CODAG_RLE_V1, TB, H> {
+    uint32_t ends[128];  // literal-list terminator positions
+};
+template <int TB, uint32_t H>
+struct WaveScratch<CODAG_DEFLATE, TB, H> {
+    DeflateLds<TB, H> t;
+};
+
+__device__ __forceinline__ uint64_t error_key(uint64_t chunk, int st) {
+    return (chunk << 4) | (uint64_t)(uint32_t)(-st);
+}
+
+// Decodes chunk c with the calling wave; returns its status.
+template <int Codec, int TB, uint32_t H>
+__device__ __forceinline__ int decode_one(const uint8_t *comp, const uint64_t *coff, uint8_t *out,
+                                          const uint64_t *ooff, uint32_t c, uint32_t *ring,
+                                          uint32_t *land, WaveScratch<Codec, TB, H> *scratch) {
+    uint64_t i0 = coff[c], i1 = coff[c + 1], o0 = ooff[c], o1 = ooff[c + 1];
+    // Decreasing offsets wrap to huge differences: one test covers both.
+    if ((((i1 - i0) | (o1 - o0)) >> 31) != 0) return CODAG_E_INVALID_ARGUMENT;
+    uint32_t in_len = (uint32_t)(i1 - i0), out_len = (uint32_t)(o1 - o0);
+    uint8_t *dst = out + o0;
+    InRing in;
+    int st;
+    if constexpr (Codec == CODAG_DEFLATE) {
+        if (in_len >= (1u << 28)) return CODAG_E_INVALID_ARGUMENT;  // bit counts fit 31 bits
+        in.init(comp + i0, in_len, ring, land);
+        st = decode_deflate<TB, H>(in, dst, out_len, &scratch->t);
+    } else {
+        if ((out_len & 7) || (reinterpret_cast<uintptr_t>(dst) & 7)) return CODAG_E_INVALID_ARGUMENT;
+        in.init(comp + i0, in_len, ring, land);
+        uint64_t *dst64 = reinterpret_cast<uint64_t *>(dst);
+        if constexpr (Codec == CODAG_RLE_V1)
+            st = decode_rle_v1(in, dst64, out_len / 8, scratch->ends);
+        else
+            st = decode_rle_v2(in, dst64, out_len / 8);
+    }
+    // The landing buffer may still have a fetch in flight: let it land before
+    // the wave moves on or exits.
+    __builtin_amdgcn_s_waitcnt(0);
+    return st;
+}
+
+__device__ __forceinline__ void report(uint32_t c, int st, int32_t *status,
+                                       unsigned long long *err) {
+    if (lane() == 0) {
+        if (status) status[c] = st;
+        if (st != CODAG_OK) atomicMin(err, (unsigned long long)error_key(c, st));
+    }
+}
+
+}  // namespace codag

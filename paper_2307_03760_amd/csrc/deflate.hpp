@@ -365,6 +365,66 @@ struct WindowOut {
     }
 };
 
+// Reads a dynamic block's header up to its code lengths (RFC 1951 3.2.7):
+// HLIT, HDIST, HCLEN, the code-length code (built into cltab, 7-bit
+// table), then the HLIT + HDIST lengths into lens.  Returns a status.
+__device__ __forceinline__ int read_code_lengths(InRing &in, BitIn &bi, uint16_t *cltab,
+                                                 CodeMeta *meta, uint16_t *sorted, uint8_t *lens,
+                                                 uint32_t &hlit, uint32_t &hdist, uint32_t &hclen) {
+    const uint32_t l = lane();
+    bi.refill(in);
+    hlit = bi.peek(5) + 257;
+    hdist = ((uint32_t)(bi.buf >> 5) & 31) + 1;
+    hclen = ((uint32_t)(bi.buf >> 10) & 15) + 4;
+    if (!bi.drop(14)) return CODAG_E_TRUNCATED;
+    if (hlit > 286 || hdist > 30) return CODAG_E_CORRUPT;
+    if (l < 19) lens[l] = 0;
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t i = 0; i < hclen; i++) {
+        bi.refill(in);
+        uint32_t v = bi.peek(3);
+        if (!bi.drop(3)) return CODAG_E_TRUNCATED;
+        lens[kCodeLenOrder[i]] = (uint8_t)v;  // same byte from every lane
+    }
+    __builtin_amdgcn_wave_barrier();
+    BuildResult cl = build_table(lens, 19, kCodeLenBits, kCodeLen, cltab, sorted, meta);
+    if (cl.left != 0) return CODAG_E_CORRUPT;
+    uint32_t idx = 0, total = hlit + hdist, prev = 0;
+    while (idx < total) {
+        bi.refill(in);
+        uint32_t e = uni((uint32_t)cltab[bi.peek(kCodeLenBits)]);
+        uint32_t sym = (e >> 4) & 511;
+        if (!bi.drop(e & 15)) return CODAG_E_TRUNCATED;
+        if (sym < 16) {
+            lens[idx] = (uint8_t)sym;  // same byte from every lane
+            prev = sym;
+            idx++;
+            continue;
+        }
+        uint32_t rep, val;
+        if (sym == 16) {
+            if (idx == 0) return CODAG_E_CORRUPT;
+            rep = 3 + bi.peek(2);
+            if (!bi.drop(2)) return CODAG_E_TRUNCATED;
+            val = prev;
+        } else if (sym == 17) {
+            rep = 3 + bi.peek(3);
+            if (!bi.drop(3)) return CODAG_E_TRUNCATED;
+            val = 0;
+        } else {
+            rep = 11 + bi.peek(7);
+            if (!bi.drop(7)) return CODAG_E_TRUNCATED;
+            val = 0;
+        }
+        if (idx + rep > total) return CODAG_E_CORRUPT;
+        for (uint32_t k = l; k < rep; k += kWave) lens[idx + k] = (uint8_t)val;
+        prev = val;
+        idx += rep;
+    }
+    __builtin_amdgcn_wave_barrier();
+    return CODAG_OK;
+}
+
 // Symbols of one Huffman block, up to and including end-of-block.  Returns
 // CODAG_OK at the end of the block or an error status; running past the end
 // of input anywhere before that point is reported as CODAG_E_TRUNCATED.
@@ -498,58 +558,9 @@ __device__ __forceinline__ int decode_deflate(InRing &in, uint8_t *out, uint32_t
             } else {
                 // Dynamic block header (RFC 1951 section 3.2.7).
                 fixed_ready = false;
-                bi.refill(in);
-                uint32_t hlit = bi.peek(5) + 257;
-                uint32_t hdist = ((uint32_t)(bi.buf >> 5) & 31) + 1;
-                uint32_t hclen = ((uint32_t)(bi.buf >> 10) & 15) + 4;
-                if (!bi.drop(14)) { st = CODAG_E_TRUNCATED; break; }
-                if (hlit > 286 || hdist > 30) { st = CODAG_E_CORRUPT; break; }
-                if (l < 19) lds->lens[l] = 0;
-                __builtin_amdgcn_wave_barrier();
-                bool trunc = false;
-                for (uint32_t i = 0; i < hclen; i++) {
-                    bi.refill(in);
-                    uint32_t v = bi.peek(3);
-                    if (!bi.drop(3)) { trunc = true; break; }
-                    lds->lens[kCodeLenOrder[i]] = (uint8_t)v;  // same byte from every lane
-                }
-                if (trunc) { st = CODAG_E_TRUNCATED; break; }
-                __builtin_amdgcn_wave_barrier();
-                BuildResult cl = build_table(lds->lens, 19, kCodeLenBits, kCodeLen, lds->dist,
-                                             lds->dist_sorted, &lds->dist_meta);
-                if (cl.left != 0) { st = CODAG_E_CORRUPT; break; }
-                uint32_t idx = 0, total = hlit + hdist, prev = 0;
-                while (idx < total) {
-                    bi.refill(in);
-                    uint32_t e = uni((uint32_t)lds->dist[bi.peek(kCodeLenBits)]);
-                    uint32_t sym = (e >> 4) & 511;
-                    if (!bi.drop(e & 15)) { st = CODAG_E_TRUNCATED; break; }
-                    if (sym < 16) {
-                        lds->lens[idx] = (uint8_t)sym;  // same byte from every lane
-                        prev = sym;
-                        idx++;
-                        continue;
-                    }
-                    uint32_t rep, val;
-                    if (sym == 16) {
-                        if (idx == 0) { st = CODAG_E_CORRUPT; break; }
-                        rep = 3 + bi.peek(2);
-                        if (!bi.drop(2)) { st = CODAG_E_TRUNCATED; break; }
-                        val = prev;
-                    } else if (sym == 17) {
-                        rep = 3 + bi.peek(3);
-                        if (!bi.drop(3)) { st = CODAG_E_TRUNCATED; break; }
-                        val = 0;
-                    } else {
-                        rep = 11 + bi.peek(7);
-                        if (!bi.drop(7)) { st = CODAG_E_TRUNCATED; break; }
-                        val = 0;
-                    }
-                    if (idx + rep > total) { st = CODAG_E_CORRUPT; break; }
-                    for (uint32_t k = l; k < rep; k += kWave) lds->lens[idx + k] = (uint8_t)val;
-                    prev = val;
-                    idx += rep;
-                }
+                uint32_t hlit, hdist, hclen;
+                st = read_code_lengths(in, bi, lds->dist, &lds->dist_meta, lds->dist_sorted,
+                                       lds->lens, hlit, hdist, hclen);
                 if (st) break;
                 __builtin_amdgcn_wave_barrier();
                 if (uni((uint32_t)lds->lens[256]) == 0) { st = CODAG_E_CORRUPT; break; }

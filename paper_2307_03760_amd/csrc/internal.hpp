@@ -1,0 +1,55 @@
+// Host-side state shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <mutex>
+
+#include "../../include/codag.h"
+#include "sched.hpp"
+
+namespace codag {
+
+constexpr int kMaxDevices = 64;
+
+struct DeviceState {
+    unsigned long long *err = nullptr;  // first-error word: (chunk << 4) | -status
+};
+
+extern std::mutex g_mu;
+extern DeviceState g_dev[kMaxDevices];
+
+// The current device's state, created on first use.
+int device_state(DeviceState **out);
+
+// Arguments of one batched launch (a captured graph is reused while they
+// stay the same).
+struct BatchArgs {
+    const uint8_t *codecs;
+    const uint8_t *comp;
+    const uint64_t *coff;
+    uint8_t *out;
+    const uint64_t *ooff;
+    uint64_t n;
+    int32_t *status;
+    const uint32_t *order;
+    uint64_t *ticks;
+    bool operator==(const BatchArgs &o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
+};
+
+}  // namespace codag
+
+struct codag_plan {
+    int device = 0;
+    int num_cus = 0;
+    codag_batch_opts opts{};
+    uint32_t *head = nullptr;  // queue position counter
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    codag::BatchArgs key{};
+    bool have_key = false;
+    codag::SchedState sched;       // learned cost model and its buffers
+    std::mutex mu;
+};

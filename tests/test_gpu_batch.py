@@ -1,0 +1,203 @@
+"""GPU parity of the batched persistent launch (codag_decompress_batch):
+mixed-codec chunk arrays decode bit-exactly like the oracle under every
+queue order, launch shape and window size, eagerly and through captured
+graphs replayed several times, and report the same per-chunk status."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+from gpu_util import batch_device_inputs, compare_chunks, oracle_mixed
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2307_03760_amd as codag
+    codag.lib()
+    return torch.device("cuda:0")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def small():
+    ch = workloads.batched_workload(seed=11, n_chunks=240)
+    ref, ref_st = oracle_mixed(ch.codecs, ch.comp, ch.chunk_offsets, ch.out_offsets)
+    assert (ref_st == 0).all()
+    return ch, ref, ref_st
+
+
+def _run(plan, ch, dev, order=None, ticks=False, reps=1, between=None):
+    import torch
+    codecs, comp, co, oo = batch_device_inputs(ch, dev)
+    out = torch.full((max(ch.out_bytes, 1),), 0xA5, dtype=torch.uint8, device=dev)
+    st = torch.full((max(ch.n_chunks, 1),), 99, dtype=torch.int32, device=dev)
+    tk = torch.zeros(max(ch.n_chunks, 1), dtype=torch.int64, device=dev) if ticks else None
+    order_t = None if order is None else torch.from_numpy(np.asarray(order, np.int32)).to(dev)
+    results = []
+    for r in range(reps):
+        if r and between is not None:
+            between(out, st)
+        plan.decompress(codecs, comp, co, out, oo, status=st[:ch.n_chunks], order=order_t,
+                        chunk_ticks=None if tk is None else tk[:ch.n_chunks])
+        torch.cuda.synchronize()
+        results.append((out[:ch.out_bytes].cpu().numpy(), st[:ch.n_chunks].cpu().numpy()))
+    return results, (None if tk is None else tk[:ch.n_chunks].cpu().numpy())
+
+
+@pytest.mark.parametrize("wpb,hist", [(1, 8), (2, 8), (4, 8), (2, 16), (1, 16)])
+def test_batch_index_order(dev, small, wpb, hist):
+    import paper_2307_03760_amd as codag
+    ch, ref, ref_st = small
+    _say(f"batch index wpb={wpb} hist={hist} chunks={ch.n_chunks}")
+    plan = codag.Plan(waves_per_block=wpb, history_kib=hist)
+    (res,), ticks = _run(plan, ch, dev, ticks=True)
+    compare_chunks(*res, ref, ref_st, ch.out_offsets)
+    assert (ticks > 0).all()
+    plan.close()
+
+
+@pytest.mark.parametrize("kind", ["reverse", "random", "codec_interleaved"])
+def test_batch_given_orders(dev, small, kind):
+    import paper_2307_03760_amd as codag
+    ch, ref, ref_st = small
+    n = ch.n_chunks
+    if kind == "reverse":
+        order = np.arange(n)[::-1]
+    elif kind == "random":
+        order = np.random.default_rng(3).permutation(n)
+    else:
+        order = np.argsort(np.arange(n) % 3, kind="stable")
+    _say(f"batch given order {kind}")
+    plan = codag.Plan(order=codag.ORDER_GIVEN, waves_per_cu=4)
+    (res,), _ = _run(plan, ch, dev, order=order)
+    compare_chunks(*res, ref, ref_st, ch.out_offsets)
+
+
+def test_batch_graph_replays(dev, small):
+    """A captured graph replayed three times, with eager work between the
+    replays (clearing the output and status), gives the full result each time."""
+    import paper_2307_03760_amd as codag
+    ch, ref, ref_st = small
+    _say("batch graph replays")
+    plan = codag.Plan(use_graph=True, order=codag.ORDER_GIVEN)
+    order = np.random.default_rng(4).permutation(ch.n_chunks)
+
+    def clear(out, st):
+        out.fill_(0x5A)
+        st.fill_(77)
+        (out[:1024].to(dev).float() * 2).sum().item()
+
+    results, _ = _run(plan, ch, dev, order=order, reps=3, between=clear)
+    for res in results:
+        compare_chunks(*res, ref, ref_st, ch.out_offsets)
+
+
+def test_batch_bad_codec_corrupt_and_bad_order(dev):
+    """Per-chunk status like the oracle for an unknown codec byte, corrupt
+    and truncated chunks inside a batch; an order entry out of range is
+    skipped and reported."""
+    import torch
+    import paper_2307_03760_amd as codag
+    ch = workloads.batched_workload(seed=12, n_chunks=60)
+    comp = ch.comp.copy()
+    codecs = ch.codecs.copy()
+    rng = np.random.default_rng(5)
+    for i in rng.choice(ch.n_chunks, 12, replace=False):
+        a, b = int(ch.chunk_offsets[i]), int(ch.chunk_offsets[i + 1])
+        comp[a + int(rng.integers(0, b - a))] ^= 0xFF
+    codecs[7] = 9
+    bad = workloads.Chunked(codecs, comp, ch.chunk_offsets, ch.out_offsets)
+    ref, ref_st = oracle_mixed(bad.codecs, bad.comp, bad.chunk_offsets, bad.out_offsets)
+    assert ref_st[7] == oracle.E_INVALID_ARGUMENT and (ref_st != 0).sum() >= 2
+    _say("batch corrupt")
+    codag.get_error()  # clear what earlier launches left
+    plan = codag.Plan()
+    (res,), _ = _run(plan, bad, dev)
+    compare_chunks(*res, ref, ref_st, bad.out_offsets)
+    rc, first = codag.get_error()
+    assert rc == int(ref_st[np.nonzero(ref_st)[0][0]]) and first == int(np.nonzero(ref_st)[0][0])
+    # An order naming a chunk that does not exist.
+    gplan = codag.Plan(order=codag.ORDER_GIVEN)
+    order = np.arange(ch.n_chunks)
+    order[5] = ch.n_chunks + 3
+    good = workloads.Chunked(ch.codecs, ch.comp, ch.chunk_offsets, ch.out_offsets)
+    (res,), _ = _run(gplan, good, dev, order=order)
+    got, got_st = res
+    assert got_st[5] == 99 and (np.delete(got_st, 5) == 0).all()
+    rc, first = codag.get_error()
+    assert rc == codag.E_INVALID_ARGUMENT and first == 5
+    torch.cuda.synchronize()
+
+
+def test_batch_empty_and_argument_checks(dev):
+    import torch
+    import paper_2307_03760_amd as codag
+    plan = codag.Plan()
+    z = torch.zeros(1, dtype=torch.int64, device=dev)
+    u8 = torch.zeros(16, dtype=torch.uint8, device=dev)
+    plan.decompress(u8[:0], u8, z, u8, z)            # zero chunks: nothing to do
+    torch.cuda.synchronize()
+    with pytest.raises(codag.CodagError):
+        codag.Plan(waves_per_block=3)
+    with pytest.raises(codag.CodagError):
+        codag.Plan(history_kib=32)
+    gplan = codag.Plan(order=codag.ORDER_GIVEN)
+    ch = workloads.batched_workload(seed=13, n_chunks=4)
+    codecs, comp, co, oo = batch_device_inputs(ch, dev)
+    out = torch.empty(ch.out_bytes, dtype=torch.uint8, device=dev)
+    with pytest.raises(codag.CodagError):
+        gplan.decompress(codecs, comp, co, out, oo)   # given order without an order
+
+
+def test_autotune_keeps_a_valid_fast_config(dev, small):
+    import torch
+    import paper_2307_03760_amd as codag
+    ch, ref, ref_st = small
+    _say("autotune")
+    plan = codag.Plan()
+    codecs, comp, co, oo = batch_device_inputs(ch, dev)
+    out = torch.empty(ch.out_bytes, dtype=torch.uint8, device=dev)
+    best = plan.autotune(codecs, comp, co, out, oo, reps=2)
+    assert best > 0
+    o = plan.opts
+    assert o["waves_per_block"] in (1, 2, 4) and o["history_kib"] in (8, 16) and o["waves_per_cu"] >= 1
+    (res,), _ = _run(plan, ch, dev)
+    compare_chunks(*res, ref, ref_st, ch.out_offsets)
+
+
+def test_batch_full_size_sampled(dev):
+    """20,000 mixed chunks (about 2 GiB out): every status OK, and a sample of
+    chunks decoded one by one by the oracle matches byte for byte."""
+    import torch
+    import paper_2307_03760_amd as codag
+    ch = workloads.batched_workload(seed=0, n_chunks=20000)
+    _say(f"batch full size: {ch.n_chunks} chunks, {ch.out_bytes / 2**30:.2f} GiB out")
+    plan = codag.Plan(use_graph=True)
+    codecs, comp, co, oo = batch_device_inputs(ch, dev)
+    out = torch.full((ch.out_bytes,), 0xA5, dtype=torch.uint8, device=dev)
+    st = torch.full((ch.n_chunks,), 99, dtype=torch.int32, device=dev)
+    plan.decompress(codecs, comp, co, out, oo, status=st)
+    torch.cuda.synchronize()
+    st_h = st.cpu().numpy()
+    assert (st_h == 0).all(), np.nonzero(st_h)[0][:10]
+    rng = np.random.default_rng(1)
+    sample = np.concatenate([rng.choice(ch.n_chunks, 150, replace=False), [0, ch.n_chunks - 1]])
+    for i in sample:
+        a, b = int(ch.chunk_offsets[i]), int(ch.chunk_offsets[i + 1])
+        oa, ob = int(ch.out_offsets[i]), int(ch.out_offsets[i + 1])
+        rst, rbytes = oracle.decode_chunk(int(ch.codecs[i]), ch.comp[a:b], ob - oa)
+        assert rst == 0
+        got = out[oa:ob].cpu().numpy().tobytes()
+        assert got == rbytes, f"chunk {i} differs"
