@@ -44,15 +44,15 @@ enum {
 
 /*
  * Tuning knobs; a zeroed struct (or NULL) selects the defaults.
- *   waves_per_block   wavefronts per workgroup: 1, 2 or 4 (default 4); waves
- *                     never synchronize with each other, so this only
- *                     shapes occupancy and dispatch.
+ *   waves_per_block   wavefronts per workgroup: 1, 2 or 4 (default 1 for
+ *                     Deflate, 4 for RLE); waves never synchronize with each
+ *                     other, so this only shapes occupancy and dispatch.
  *   lit_table_bits    Deflate literal/length lookup-table bits, 9 or 10
- *                     (default 10); longer codes take a slower path.
- *   history_kib       Deflate history window kept in LDS per wave: 8, 16 or
- *                     32 KiB (default 8).  Back-references reaching further
- *                     read the already written output from HBM.  With 32 the
- *                     workgroup holds one wave.
+ *                     (default 9); longer codes take a slower path.
+ *   history_kib       Deflate output window kept in LDS per wave: 2, 4, 8,
+ *                     16 or 32 KiB (default 4).  Back-references reaching
+ *                     further read the already written output from HBM.
+ *                     With 32 the workgroup holds one wave.
  *   chunk_ticks       optional device array (n_chunks uint64): receives each
  *                     chunk's decode time in shader clock cycles.
  */
@@ -148,8 +148,8 @@ enum {
  *   waves_per_cu      resident waves per CU in the persistent grid (default:
  *                     as many as the per-wave LDS allows, at most 16).
  *   waves_per_block   1, 2 or 4 (default 2).
- *   lit_table_bits    Deflate literal/length table bits; only 10 here.
- *   history_kib       Deflate LDS history window, 8 or 16 KiB (default 8).
+ *   lit_table_bits    Deflate literal/length table bits; only 9 here.
+ *   history_kib       Deflate LDS output window, 4, 8 or 16 KiB (default 4).
  *   order             CODAG_ORDER_* (default CODAG_ORDER_INDEX).
  *   use_graph         nonzero: capture the launch sequence (queue reset,
  *                     scheduling steps, decode) in a hipGraph once per set of

@@ -88,11 +88,14 @@ using namespace codag;
 namespace {
 
 constexpr uint32_t kLdsPerCu = 160 * 1024;
+constexpr int kBatchTB = 9;  // Deflate literal/length table bits in the batched kernel
 constexpr int kVgprWavesPerSimd = 5;  // the decoders use up to 92 VGPRs
 
 
 uint32_t lds_per_wave(int hist_kib) {
-    return hist_kib == 16 ? batch_lds_per_wave<10, 16384>() : batch_lds_per_wave<10, 8192>();
+    return hist_kib == 16  ? batch_lds_per_wave<kBatchTB, 16384>()
+           : hist_kib == 8 ? batch_lds_per_wave<kBatchTB, 8192>()
+                           : batch_lds_per_wave<kBatchTB, 4096>();
 }
 
 int max_waves_per_cu(int hist_kib, int wpb) {
@@ -116,12 +119,12 @@ int resolve_opts(const codag_batch_opts *in, codag_batch_opts *o) {
     codag_batch_opts r{};
     if (in) r = *in;
     if (r.waves_per_block == 0) r.waves_per_block = 2;
-    if (r.lit_table_bits == 0) r.lit_table_bits = 10;
-    if (r.history_kib == 0) r.history_kib = 8;
+    if (r.lit_table_bits == 0) r.lit_table_bits = kBatchTB;
+    if (r.history_kib == 0) r.history_kib = 4;
     if (r.waves_per_block != 1 && r.waves_per_block != 2 && r.waves_per_block != 4)
         return CODAG_E_INVALID_ARGUMENT;
-    if (r.lit_table_bits != 10) return CODAG_E_INVALID_ARGUMENT;
-    if (r.history_kib != 8 && r.history_kib != 16) return CODAG_E_INVALID_ARGUMENT;
+    if (r.lit_table_bits != kBatchTB) return CODAG_E_INVALID_ARGUMENT;
+    if (r.history_kib != 4 && r.history_kib != 8 && r.history_kib != 16) return CODAG_E_INVALID_ARGUMENT;
     if (r.order < CODAG_ORDER_INDEX || r.order > CODAG_ORDER_LEARNED) return CODAG_E_INVALID_ARGUMENT;
     if (r.waves_per_cu < 0 || r.waves_per_cu > 64) return CODAG_E_INVALID_ARGUMENT;
     if (r.waves_per_cu == 0) r.waves_per_cu = max_waves_per_cu(r.history_kib, r.waves_per_block);
@@ -133,7 +136,7 @@ template <uint32_t H, int WPB>
 void launch_decode(codag_plan *p, const BatchArgs &a, const uint32_t *order, unsigned long long *err,
                    hipStream_t s) {
     uint32_t blocks = (uint32_t)std::max<int64_t>(1, ((int64_t)p->num_cus * p->opts.waves_per_cu) / WPB);
-    hipLaunchKernelGGL((decode_batch<10, H, WPB>), dim3(blocks), dim3(kWave * WPB), 0, s, a.codecs,
+    hipLaunchKernelGGL((decode_batch<kBatchTB, H, WPB>), dim3(blocks), dim3(kWave * WPB), 0, s, a.codecs,
                        a.comp, a.coff, a.out, a.ooff, (uint32_t)a.n, order, p->head, a.status, err,
                        a.ticks);
 }
@@ -150,16 +153,22 @@ int enqueue(codag_plan *p, const BatchArgs &a, unsigned long long *err, hipStrea
         if (st) return st;
         order = p->sched.order;
     }
-    bool big = p->opts.history_kib == 16;
+    const int h = p->opts.history_kib;
     switch (p->opts.waves_per_block) {
         case 1:
-            big ? launch_decode<16384, 1>(p, a, order, err, s) : launch_decode<8192, 1>(p, a, order, err, s);
+            h == 16 ? launch_decode<16384, 1>(p, a, order, err, s)
+            : h == 8 ? launch_decode<8192, 1>(p, a, order, err, s)
+                     : launch_decode<4096, 1>(p, a, order, err, s);
             break;
         case 4:
-            big ? launch_decode<16384, 4>(p, a, order, err, s) : launch_decode<8192, 4>(p, a, order, err, s);
+            h == 16 ? launch_decode<16384, 4>(p, a, order, err, s)
+            : h == 8 ? launch_decode<8192, 4>(p, a, order, err, s)
+                     : launch_decode<4096, 4>(p, a, order, err, s);
             break;
         default:
-            big ? launch_decode<16384, 2>(p, a, order, err, s) : launch_decode<8192, 2>(p, a, order, err, s);
+            h == 16 ? launch_decode<16384, 2>(p, a, order, err, s)
+            : h == 8 ? launch_decode<8192, 2>(p, a, order, err, s)
+                     : launch_decode<4096, 2>(p, a, order, err, s);
     }
     return hipGetLastError() == hipSuccess ? CODAG_OK : CODAG_E_HIP;
 }
@@ -330,7 +339,7 @@ int codag_autotune(codag_plan *plan, const uint8_t *codecs, const uint8_t *comp_
     };
     // Coordinate search: window size, then waves per workgroup, then the
     // number of resident waves per CU.
-    for (int hist : {8, 16}) {
+    for (int hist : {4, 8, 16}) {
         codag_batch_opts o = base;
         o.history_kib = hist;
         o.waves_per_cu = 0;

@@ -100,6 +100,12 @@ int launch_deflate(const uint8_t *comp, const uint64_t *coff, uint8_t *out, cons
     if (hist_kib == 16)
         return launch_plain<CODAG_DEFLATE, TB, 16384>(comp, coff, out, ooff, n, wpb, status, err,
                                                       ticks, stream);
+    if (hist_kib == 2)
+        return launch_plain<CODAG_DEFLATE, TB, 2048>(comp, coff, out, ooff, n, wpb, status, err,
+                                                     ticks, stream);
+    if (hist_kib == 4)
+        return launch_plain<CODAG_DEFLATE, TB, 4096>(comp, coff, out, ooff, n, wpb, status, err,
+                                                     ticks, stream);
     if (hist_kib == 32)
         return launch_wpb<CODAG_DEFLATE, TB, 32768, 1>(comp, coff, out, ooff, n, status, err,
                                                        ticks, stream);
@@ -119,11 +125,13 @@ int codag_decompress_ex(int codec, const uint8_t *comp_buf, const uint64_t *chun
     if (n_chunks == 0) return CODAG_OK;
     if (!comp_buf || !chunk_offsets || !out_buf || !out_offsets) return CODAG_E_INVALID_ARGUMENT;
     if (n_chunks >= (1ull << 32) - 64) return CODAG_E_INVALID_ARGUMENT;
-    int wpb = opts && opts->waves_per_block ? opts->waves_per_block : 4;
-    int tb = opts && opts->lit_table_bits ? opts->lit_table_bits : 10;
-    int hist = opts && opts->history_kib ? opts->history_kib : 8;
+    // Defaults: RLE waves share a workgroup; Deflate waves go one per
+    // workgroup with a small window and table, for the most resident waves.
+    int wpb = opts && opts->waves_per_block ? opts->waves_per_block : codec == CODAG_DEFLATE ? 1 : 4;
+    int tb = opts && opts->lit_table_bits ? opts->lit_table_bits : 9;
+    int hist = opts && opts->history_kib ? opts->history_kib : 4;
     if ((wpb != 1 && wpb != 2 && wpb != 4) || (tb != 9 && tb != 10) ||
-        (hist != 8 && hist != 16 && hist != 32))
+        (hist != 2 && hist != 4 && hist != 8 && hist != 16 && hist != 32))
         return CODAG_E_INVALID_ARGUMENT;
     uint64_t *ticks = opts ? opts->chunk_ticks : nullptr;
     DeviceState *ds = nullptr;

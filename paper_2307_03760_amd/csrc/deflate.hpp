@@ -425,12 +425,17 @@ __device__ __forceinline__ int read_code_lengths(InRing &in, BitIn &bi, uint16_t
     return CODAG_OK;
 }
 
+// Returned by the one-symbol form of inflate_symbols after a literal or a
+// copy (not a status).
+constexpr int kMore = 1;
+
 // Symbols of one Huffman block, up to and including end-of-block.  Returns
 // CODAG_OK at the end of the block or an error status; running past the end
 // of input anywhere before that point is reported as CODAG_E_TRUNCATED.
 // The loop is kept small and with few exits: literals first, then
-// length/distance pairs; everything rare leaves the loop.
-template <int TB, uint32_t H>
+// length/distance pairs; everything rare leaves the loop.  With ONE, it
+// returns kMore after the first literal or copy.
+template <int TB, uint32_t H, bool ONE = false>
 __device__ __forceinline__ int inflate_symbols(InRing &in, BitIn &bi, WindowOut<H> &o,
                                                DeflateLds<TB, H> *lds, bool have_dist,
                                                uint32_t len_tab, uint32_t dist_tab) {
@@ -445,6 +450,7 @@ __device__ __forceinline__ int inflate_symbols(InRing &in, BitIn &bi, WindowOut<
                 break;
             }
             o.put_literal(e >> 4);
+            if (ONE) return kMore;
             continue;
         }
         if ((e >> 13) == kSlow) e = slow_symbol(bi, &lds->lit_meta, lds->lit_sorted, kLitLen);
@@ -456,6 +462,7 @@ __device__ __forceinline__ int inflate_symbols(InRing &in, BitIn &bi, WindowOut<
                 break;
             }
             o.put_literal((e >> 4) & 255);
+            if (ONE) return kMore;
             continue;
         }
         if (kind != kBase) {  // end of block, or an invalid code
@@ -491,8 +498,227 @@ __device__ __forceinline__ int inflate_symbols(InRing &in, BitIn &bi, WindowOut<
             break;
         }
         o.copy(dist, len);
+        if (ONE) return kMore;
     }
     return bi.remain < 0 ? CODAG_E_TRUNCATED : st;
+}
+
+// ---------------------------------------------------------------------------
+// Batched symbol decoding.
+//
+// The serial dependency of Huffman decoding is the position of the next
+// code.  Here every lane decodes, from its own bit offset b + lane, the whole
+// token that would start there -- a literal, or a length code with its extra
+// bits and the distance code with its extra bits -- with two table lookups
+// issued by all lanes at once.  A wave-uniform walk then follows the real
+// token starts through those 64 candidates with one lane read per token, and
+// collects up to 64 tokens (at most kBatchOut output bytes) in registers.
+// The batch is then written out: literals by one store per lane, copies
+// whose source lies before the batch lane-parallel (one lane per copy), and
+// the few copies that read bytes of the batch itself one after another.
+// Anything unusual (codes longer than the tables, invalid codes, an output
+// overflow, a distance reaching before the chunk) ends the batch and goes
+// through one step of the symbol-at-a-time loop above, so the statuses are
+// exactly that loop's.
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t kBatchOut = 1024;
+enum : uint32_t { kTokLit = 0, kTokMatch = 1, kTokEob = 2, kTokOther = 3 };
+
+// Length and distance bases and extra-bit counts (RFC 1951 section 3.2.5)
+// in closed form.
+__device__ __forceinline__ uint32_t length_extra(uint32_t k) {  // k = symbol - 257
+    return (k < 8 || k == 28) ? 0 : (k >> 2) - 1;
+}
+__device__ __forceinline__ uint32_t length_base(uint32_t k) {
+    return k < 8 ? k + 3 : k == 28 ? 258 : ((4 + (k & 3)) << ((k >> 2) - 1)) + 3;
+}
+__device__ __forceinline__ uint32_t dist_extra(uint32_t d) { return d < 4 ? 0 : (d >> 1) - 1; }
+__device__ __forceinline__ uint32_t dist_base(uint32_t d) {
+    return d < 4 ? d + 1 : ((2 + (d & 1)) << ((d >> 1) - 1)) + 1;
+}
+
+// The token starting at bit b + lane (b + 63 at most): info = bits used |
+// kind << 6 | (literal byte or match length) << 8, and a match's distance.
+// The lane's 64 input bits come from the wave-uniform words s0..s4 (input
+// words b/32 .. b/32 + 4); a length code with its extra bits, the distance
+// code and its extra bits take at most 36 bits.
+template <int TB, uint32_t H>
+__device__ __forceinline__ void lane_token(uint32_t s0, uint32_t s1, uint32_t s2, uint32_t s3,
+                                           uint32_t s4, uint32_t b, const DeflateLds<TB, H> *lds,
+                                           bool have_dist, uint32_t &info, uint32_t &dist) {
+    const uint32_t a = (b & 31) + lane();
+    const uint32_t k = a >> 5, sh = a & 31;
+    const uint32_t wa = k == 0 ? s0 : k == 1 ? s1 : s2;
+    const uint32_t wb = k == 0 ? s1 : k == 1 ? s2 : s3;
+    const uint32_t wc = k == 0 ? s2 : k == 1 ? s3 : s4;
+    const uint64_t x = ((uint64_t)__builtin_amdgcn_alignbit(wc, wb, sh) << 32) |
+                       __builtin_amdgcn_alignbit(wb, wa, sh);
+    const uint32_t e = lds->lit[(uint32_t)x & ((1u << TB) - 1)];
+    const uint32_t kind = e >> 13, cl = e & 15, sym = (e >> 4) & 511;
+    info = kTokOther << 6;
+    dist = 0;
+    if (kind == kLit) {
+        info = cl | (kTokLit << 6) | (sym << 8);
+    } else if (kind == kEob) {
+        info = cl | (kTokEob << 6);
+    } else if (kind == kBase && have_dist) {
+        const uint32_t kk = sym - 257, ex = length_extra(kk);
+        const uint32_t len = length_base(kk) + ((uint32_t)(x >> cl) & ((1u << ex) - 1));
+        const uint32_t p2 = cl + ex;
+        const uint32_t d = lds->dist[(uint32_t)(x >> p2) & ((1u << kDistBits) - 1)];
+        if ((d >> 13) == kBase) {
+            const uint32_t dcl = d & 15, ds = (d >> 4) & 31, dex = dist_extra(ds);
+            dist = dist_base(ds) + ((uint32_t)(x >> (p2 + dcl)) & ((1u << dex) - 1));
+            info = (p2 + dcl + dex) | (kTokMatch << 6) | (len << 8);
+        }
+    }
+}
+
+template <int TB, uint32_t H>
+__device__ __forceinline__ int inflate_batched(InRing &in, BitIn &bi, WindowOut<H> &o,
+                                               DeflateLds<TB, H> *lds, bool have_dist,
+                                               uint32_t len_tab, uint32_t dist_tab) {
+    const uint32_t l = lane();
+    uint32_t p = 8 * bi.next - bi.cnt;  // bit position of the next code
+    // Input words [cend - 64, cend), one per lane, read from the ring once
+    // per 236 bytes or so; a window takes its five words out with readlane.
+    uint32_t cache = 0, cend = 0;
+    for (;;) {
+        o.make_room(kBatchOut);
+        // ---- collect a batch of tokens
+        uint32_t ntok = 0, bout = 0;
+        uint32_t tok = 0, tdist = 0;  // token k in lane k: length << 16 | literal, flag 0x8000 = copy
+        uint32_t stop = 0;            // 1 full, 2 end of block, 3 one symbol the slow way
+        const uint32_t total0 = o.pos;
+        do {
+            const uint32_t wi = p >> 5;
+            if (wi + 5 > cend) {
+                in.ensure(4 * (wi + 64) + 4);
+                cache = in.word(wi + l);
+                cend = wi + 64;
+            }
+            const uint32_t c0 = wi + 64 - cend;
+            uint32_t info, dist;
+            lane_token<TB, H>(readlane(cache, c0), readlane(cache, c0 + 1), readlane(cache, c0 + 2),
+                              readlane(cache, c0 + 3), readlane(cache, c0 + 4), p, lds, have_dist,
+                              info, dist);
+            // The walk from offset 0 has two exits: a token it cannot take
+            // here, and the end of the window or of the batch.  Flags are
+            // computed with integer arithmetic rather than comparisons, so the
+            // loop stays in scalar registers (all values are below 2^31).
+            uint32_t t = 0, inf, bad;
+            for (;;) {
+                inf = readlane(info, t);
+                const uint32_t d = readlane(dist, t);  // 0 unless a copy
+                const uint32_t kind = (inf >> 6) & 3, v = inf >> 8;
+                const uint32_t m = 0u - (kind & 1);  // all ones for a copy
+                const uint32_t total = total0 + bout;
+                const uint32_t len = 1 + ((v - 1) & m);
+                bad = (kind >> 1) | (uint32_t)((int32_t)(o.cap - (total + len)) >> 31) |
+                      (uint32_t)((int32_t)(total - d) >> 31);
+                if (bad) break;
+                const uint32_t tv = (len << 16) | (v ^ ((v ^ 0x8000u) & m));
+                tok = l == ntok ? tv : tok;
+                tdist = l == ntok ? d : tdist;
+                t += inf & 63;
+                ntok++;
+                bout += len;
+                if ((t >> 6) | (ntok >> 6) | (uint32_t)((int32_t)(kBatchOut - 258 - bout) >> 31)) break;
+            }
+            if (bad) {
+                if (((inf >> 6) & 3) == kTokEob) {
+                    t += inf & 63;
+                    stop = 2;
+                } else {
+                    stop = 3;
+                }
+            } else if (ntok == kWave || bout > kBatchOut - 258) {
+                stop = 1;  // batch full
+            }
+            p += t;
+        } while (stop == 0);
+
+        // ---- write the batch
+        if (ntok) {
+            const bool valid = l < ntok;
+            const uint32_t len = valid ? tok >> 16 : 0;
+            const bool is_copy = valid && (tok & 0x8000u);
+            const uint32_t start = o.o0 + total0;  // first byte of the batch (window coordinates)
+            const uint32_t dst = start + wave_inclusive_sum32(len) - len;
+            if (valid && !is_copy) o.win[o.slot(dst)] = (uint8_t)tok;
+            const uint32_t src = dst - tdist;
+            const bool before = is_copy && src + len <= start;  // source entirely before the batch
+            // Bytes below lds_from may be overwritten in the window by this
+            // batch; they were flushed to HBM before it started.
+            const int32_t lds_from = (int32_t)(start + bout) - (int32_t)H;
+            if (ballot(before && (int32_t)src < lds_from)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            for (uint32_t r = 0; ballot(before && r < len); r += 16) {
+                if (before && r < len) {
+                    // Sixteen source bytes as five aligned words (from the
+                    // window, and from HBM where they fall below lds_from),
+                    // all loads issued before any is used; then byte stores.
+                    // HBM words may take up to three bytes either side of the
+                    // copy's range: the same aligned word, so the same
+                    // allocation; those bytes are discarded.
+                    const uint32_t n = min(len - r, 16u), q0 = src + r;
+                    const uint32_t a0 = q0 & ~3u, sh = q0 & 3;
+                    uint32_t w[5], g[5];
+#pragma unroll
+                    for (uint32_t j = 0; j < 5; j++)
+                        w[j] = *reinterpret_cast<const uint32_t *>(o.win + o.slot(a0 + 4 * j));
+                    const int32_t nglob = lds_from - (int32_t)q0;  // leading bytes taken from HBM
+                    if (nglob > 0) {
+                        const uint32_t *gp = reinterpret_cast<const uint32_t *>(o.base + a0);
+#pragma unroll
+                        for (uint32_t j = 0; j < 5; j++) g[j] = gp[j];
+                    }
+#pragma unroll
+                    for (uint32_t j = 0; j < 4; j++) {
+                        uint32_t v = __builtin_amdgcn_alignbyte(w[j + 1], w[j], sh);
+                        if (nglob > 4 * (int32_t)j) {
+                            uint32_t gv = __builtin_amdgcn_alignbyte(g[j + 1], g[j], sh);
+                            int32_t kb = nglob - 4 * (int32_t)j;  // bytes of this word from HBM
+                            uint32_t m = kb >= 4 ? 0xffffffffu : (1u << (8 * kb)) - 1;
+                            v = (gv & m) | (v & ~m);
+                        }
+#pragma unroll
+                        for (uint32_t b = 0; b < 4; b++)
+                            if (4 * j + b < n) o.win[o.slot(dst + r + 4 * j + b)] = (uint8_t)(v >> (8 * b));
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            // Copies that read bytes of this batch, in order (their sources
+            // are recent, so always in the window).
+            uint64_t m = ballot(is_copy && !before);
+            while (m) {
+                uint32_t k = (uint32_t)__builtin_ctzll(m);
+                m &= m - 1;
+                uint32_t cd = readlane(dst, k), cs = readlane(tdist, k), cl = readlane(len, k);
+                if (cs >= cl) {
+                    for (uint32_t i = l; i < cl; i += kWave) o.win[o.slot(cd + i)] = o.win[o.slot(cd - cs + i)];
+                } else {
+                    uint32_t rr = l % cs, step = kWave % cs;
+                    for (uint32_t i = l; i < cl; i += kWave) {
+                        o.win[o.slot(cd + i)] = o.win[o.slot(cd - cs + rr)];
+                        rr += step;
+                        if (rr >= cs) rr -= cs;
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+            o.pos += bout;
+            o.room -= bout;
+        }
+        if (stop == 1) continue;
+        bi.seek(in, p >> 3);
+        bi.skip(p & 7);
+        if (stop == 2) return bi.remain < 0 ? CODAG_E_TRUNCATED : CODAG_OK;
+        int st = inflate_symbols<TB, H, true>(in, bi, o, lds, have_dist, len_tab, dist_tab);
+        if (st != kMore) return st;
+        p = 8 * bi.next - bi.cnt;
+    }
 }
 
 template <int TB, uint32_t H>
@@ -578,7 +804,7 @@ __device__ __forceinline__ int decode_deflate(InRing &in, uint8_t *out, uint32_t
                 }
                 have_dist = dr.total != 0;
             }
-            st = inflate_symbols<TB, H>(in, bi, o, lds, have_dist, len_tab, dist_tab);
+            st = inflate_batched<TB, H>(in, bi, o, lds, have_dist, len_tab, dist_tab);
             if (st) break;
         }
         if (last) break;

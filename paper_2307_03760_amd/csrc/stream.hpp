@@ -21,10 +21,13 @@
 
 namespace codag {
 
-constexpr uint32_t kRingBytes = 2048;
+#ifndef CODAG_FETCH_KIB
+#define CODAG_FETCH_KIB 1
+#endif
+constexpr uint32_t kFetchBytes = 1024 * CODAG_FETCH_KIB;  // one or more 64 lanes x 16 bytes
+constexpr uint32_t kRingBytes = 2 * kFetchBytes;
 constexpr uint32_t kRingWords = kRingBytes / 4;
 constexpr uint32_t kRingLdsWords = kRingWords + 4;  // + mirror of the first 16 bytes
-constexpr uint32_t kFetchBytes = 1024;              // 64 lanes x 16 bytes
 constexpr uint32_t kLandWords = kFetchBytes / 4;
 
 typedef __attribute__((address_space(3))) void lds_void;
@@ -39,15 +42,18 @@ struct InRing {
     const uint8_t *gbase;  // 16-byte aligned
     uint32_t skip;         // chunk start relative to gbase (0..15)
     uint32_t gend;         // one past the chunk's last byte, relative to gbase
-    uint32_t loaded;       // bytes [loaded - 2048, loaded) are in the ring
+    uint32_t loaded;       // bytes [loaded - kRingBytes, loaded) are in the ring
     uint32_t *ring;        // this wave's ring (kRingLdsWords words)
     uint32_t *land;        // this wave's landing buffer (kLandWords words)
 
-    // Start fetching [loaded, loaded + 1024) into the landing buffer.
+    // Start fetching [loaded, loaded + kFetchBytes) into the landing buffer.
     __device__ __forceinline__ void issue() {
-        uint32_t at = loaded + 16 * lane();
-        if (at < gend)
-            __builtin_amdgcn_global_load_lds(gbase + at, (lds_void *)land, 16, 0, 0);
+#pragma unroll
+        for (uint32_t k = 0; k < kFetchBytes / 1024; k++) {
+            uint32_t at = loaded + 1024 * k + 16 * lane();
+            if (at < gend)
+                __builtin_amdgcn_global_load_lds(gbase + at, (lds_void *)(land + 256 * k), 16, 0, 0);
+        }
     }
 
     __device__ __forceinline__ void init(const uint8_t *chunk, uint32_t len, uint32_t *ring_lds,
@@ -63,30 +69,33 @@ struct InRing {
         issue();
     }
 
-    // Move the landed kilobyte into the ring and start fetching the next.
+    // Move the landed bytes into the ring and start fetching the next.
     __device__ __forceinline__ void commit() {
-        uint32_t at = loaded + 16 * lane();
         wait_vm();
-        uint4 v = reinterpret_cast<const uint4 *>(land)[lane()];
-        if (at + 16 > gend) {  // zero the bytes past the end of the chunk
-            uint32_t valid = at < gend ? gend - at : 0;
-            uint32_t w[4] = {v.x, v.y, v.z, v.w};
+        const uint32_t half = (loaded / kFetchBytes) & 1;
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                int keep = (int)valid - 4 * k;
-                uint32_t m = keep >= 4 ? 0xffffffffu : keep <= 0 ? 0u : ((1u << (8 * keep)) - 1);
-                w[k] &= m;
+        for (uint32_t k = 0; k < kFetchBytes / 1024; k++) {
+            uint32_t at = loaded + 1024 * k + 16 * lane();
+            uint4 v = reinterpret_cast<const uint4 *>(land)[64 * k + lane()];
+            if (at + 16 > gend) {  // zero the bytes past the end of the chunk
+                uint32_t valid = at < gend ? gend - at : 0;
+                uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    int keep = (int)valid - 4 * j;
+                    uint32_t m = keep >= 4 ? 0xffffffffu : keep <= 0 ? 0u : ((1u << (8 * keep)) - 1);
+                    w[j] &= m;
+                }
+                v = make_uint4(w[0], w[1], w[2], w[3]);
             }
-            v = make_uint4(w[0], w[1], w[2], w[3]);
+            reinterpret_cast<uint4 *>(ring)[half * (kFetchBytes / 16) + 64 * k + lane()] = v;
+            if (half == 0 && k == 0 && lane() == 0) reinterpret_cast<uint4 *>(ring)[kRingBytes / 16] = v;
         }
-        uint32_t half = (loaded / kFetchBytes) & 1;
-        reinterpret_cast<uint4 *>(ring)[half * 64 + lane()] = v;
-        if (half == 0 && lane() == 0) reinterpret_cast<uint4 *>(ring)[128] = v;
         loaded += kFetchBytes;
         issue();
     }
 
-    // Make bytes [end - 1024, end) readable.
+    // Make bytes [end - kFetchBytes, end) readable.
     __device__ __forceinline__ void ensure(uint32_t end) {
         while (loaded < end) commit();
     }

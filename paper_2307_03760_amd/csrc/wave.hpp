@@ -66,6 +66,22 @@ __device__ __forceinline__ uint64_t wave_inclusive_sum(uint64_t x) {
     return x;
 }
 
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ uint32_t dpp32(uint32_t x) {
+    return __builtin_amdgcn_update_dpp(0u, x, Ctrl, RowMask, 0xf, true);
+}
+
+// Inclusive prefix sum over the 64 lanes (modulo 2^32); all lanes active.
+__device__ __forceinline__ uint32_t wave_inclusive_sum32(uint32_t x) {
+    x += dpp32<kDppRowShr1, 0xf>(x);
+    x += dpp32<kDppRowShr2, 0xf>(x);
+    x += dpp32<kDppRowShr4, 0xf>(x);
+    x += dpp32<kDppRowShr8, 0xf>(x);
+    x += dpp32<kDppRowBcast15, 0xa>(x);
+    x += dpp32<kDppRowBcast31, 0xc>(x);
+    return x;
+}
+
 __device__ __forceinline__ uint32_t bswap32(uint32_t x) { return __builtin_bswap32(x); }
 
 // Zigzag: 0, 1, 2, 3, 4 code 0, -1, 1, -2, 2.

@@ -61,6 +61,15 @@ def test_deflate_small(dev, tb):
     assert (assert_parity(oracle.DEFLATE, ch, dev, lit_table_bits=tb) == 0).all()
 
 
+@pytest.mark.parametrize("hist,wpb", [(2, 1), (4, 2), (8, 4), (16, 1), (32, 1)])
+def test_deflate_window_sizes(dev, hist, wpb):
+    """Every output-window size: back-references beyond the window read the
+    already written output from HBM."""
+    ch = workloads.deflate_workload(seed=6, total_bytes=40 * 65536 + 777)
+    _say(f"deflate window {hist} KiB wpb={wpb} chunks={ch.n_chunks}")
+    assert (assert_parity(oracle.DEFLATE, ch, dev, history_kib=hist, waves_per_block=wpb) == 0).all()
+
+
 def test_rle_v2_each_subencoding(dev):
     rng = np.random.default_rng(21)
     blobs, sizes = [], []
