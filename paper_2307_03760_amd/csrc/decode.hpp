@@ -15,10 +15,6 @@ struct WaveScratch {
     uint32_t unused;
 };
 template <int TB, uint32_t H>
-struct WaveScratch<CODAG_RLE_V1, TB, H> {
-    uint32_t ends[128];  // literal-list terminator positions
-};
-template <int TB, uint32_t H>
 struct WaveScratch<CODAG_DEFLATE, TB, H> {
     DeflateLds<TB, H> t;
 };
@@ -48,7 +44,7 @@ __device__ __forceinline__ int decode_one(const uint8_t *comp, const uint64_t *c
         in.init(comp + i0, in_len, ring, land);
         uint64_t *dst64 = reinterpret_cast<uint64_t *>(dst);
         if constexpr (Codec == CODAG_RLE_V1)
-            st = decode_rle_v1(in, dst64, out_len / 8, scratch->ends);
+            st = decode_rle_v1(in, dst64, out_len / 8);
         else
             st = decode_rle_v2(in, dst64, out_len / 8);
     }

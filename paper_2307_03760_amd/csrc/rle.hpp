@@ -28,95 +28,115 @@ __device__ __forceinline__ uint64_t low_bytes(uint64_t x, uint32_t nb) {
     return nb >= 8 ? x : x & ((1ull << (8 * nb)) - 1);
 }
 
-// Unsigned base-128 varint at byte position pos (wave-uniform).  Bytes past
-// the end of the chunk read as zero, i.e. as terminators, so a varint cut off
-// by the end is seen ending past `end` and reported TRUNCATED.
+// An unsigned base-128 varint from its bytes: x = the first eight, y = the
+// next two (little-endian).  Returns its length in bytes (9 or 10 for the
+// long forms), or 0 if it is longer than ten bytes or has bits above bit 63.
+// Bytes past the end of the chunk read as zero, i.e. as terminators, so a
+// varint cut off by the end is seen ending past `end` (the caller reports
+// TRUNCATED).
+__device__ __forceinline__ uint32_t varint_bytes(uint64_t x, uint32_t y, uint64_t &z) {
+    uint64_t t = ~x & 0x8080808080808080ull;
+    if (t) {
+        uint32_t nb = (uint32_t)(__builtin_ctzll(t) >> 3) + 1;
+        z = pack7(low_bytes(x, nb));
+        return nb;
+    }
+    uint32_t b8 = y & 0xff, b9 = (y >> 8) & 0xff;
+    if ((b8 & 0x80) && b9 > 1) return 0;  // bits above bit 63, or an 11th byte
+    uint32_t nb = (b8 & 0x80) ? 10 : 9;
+    z = pack7(x) | ((uint64_t)(b8 & 0x7f) << 56) | (nb == 10 ? (uint64_t)b9 << 63 : 0);
+    return nb;
+}
+
+// Unsigned base-128 varint at byte position pos (wave-uniform).
 __device__ __forceinline__ int read_varint(InRing &in, uint32_t &pos, uint32_t end, uint64_t &z) {
     in.ensure(pos + 24);
-    uint64_t x = in.peek8(pos);
-    uint64_t t = ~x & 0x8080808080808080ull;
-    uint32_t nb;
-    uint64_t v;
-    if (t) {
-        nb = (uint32_t)(__builtin_ctzll(t) >> 3) + 1;
-        v = pack7(low_bytes(x, nb));
-    } else {
-        uint64_t y = in.peek8(pos + 8);
-        uint32_t b8 = (uint32_t)(y & 0xff), b9 = (uint32_t)((y >> 8) & 0xff);
-        if (b8 & 0x80) {
-            if (b9 > 1) {
-                return CODAG_E_CORRUPT;  // bits above bit 63, or an 11th byte
-            }
-            nb = 10;
-        } else {
-            nb = 9;
-        }
-        v = pack7(x) | ((uint64_t)(b8 & 0x7f) << 56) | (nb == 10 ? (uint64_t)b9 << 63 : 0);
-    }
+    uint64_t lo, hi;
+    ring_read16(in, pos, lo, hi);
+    uint32_t nb = uni(varint_bytes(uni64(lo), uni((uint32_t)hi), z));
+    if (nb == 0) return CODAG_E_CORRUPT;
     if (pos + nb > end) return CODAG_E_TRUNCATED;
     pos += nb;
-    z = v;
     return CODAG_OK;
 }
 
-// A literal list of `count` zigzag varints starting at pos, lane-parallel.
-// Each pass looks at a 256-byte window (4 bytes per lane): terminator bytes
-// (bit 7 clear) are counted per lane, an exclusive scan built from three
-// ballots numbers them, their positions go to LDS, and then lane k decodes
-// varint k from the bytes between terminators k-1 and k.
+// Terminator bytes (bit 7 clear) of a little-endian word, one bit per byte.
+__device__ __forceinline__ uint32_t terminators4(uint32_t w) {
+    uint32_t t = (~w & 0x80808080u) >> 7;  // bits 0, 8, 16, 24
+    return (t | (t >> 7) | (t >> 14) | (t >> 21)) & 15;
+}
+
+// A literal list of `count` zigzag varints starting at pos, 512 bytes per
+// pass: lane l holds bytes [p0 + 8l, p0 + 8l + 8) and the 16 before them.
+// Each lane counts the terminator bytes (bit 7 clear) in its 8; a wave
+// prefix sum numbers them, a wave running maximum gives the position after
+// the last terminator of the lanes below, and then every lane decodes, from
+// its registers, the varints whose terminators it holds and stores them at
+// their index -- no compaction through LDS.
 __device__ __forceinline__ int rle_literal_list(InRing &in, uint32_t &pos, uint32_t end,
-                                                uint32_t count, uint64_t *out, uint32_t *ends) {
+                                                uint32_t count, uint64_t *out) {
+    const uint32_t l = lane();
     uint32_t done = 0;
     while (done < count) {
-        uint32_t p0 = pos & ~3u;
-        in.ensure(p0 + 272);
-        uint32_t w = in.word((p0 >> 2) + lane());
-        uint32_t at = p0 + 4 * lane();
-        uint32_t tm = 0;
+        const uint32_t p0 = pos & ~7u;
+        in.ensure(p0 + 528);
+        const uint32_t at = p0 + 8 * l, wb = at >> 2;
+        uint32_t wd[6];
 #pragma unroll
-        for (int k = 0; k < 4; k++)
-            if (!((w >> (8 * k + 7)) & 1) && at + k >= pos) tm |= 1u << k;
-        uint32_t cnt = __builtin_popcount(tm);
-        uint64_t b0 = ballot(cnt & 1), b1 = ballot(cnt & 2), b2 = ballot(cnt & 4);
-        uint32_t idx = count_below(b0) + 2 * count_below(b1) + 4 * count_below(b2);
-        uint32_t total = (uint32_t)(__builtin_popcountll(b0) + 2 * __builtin_popcountll(b1) +
-                                    4 * __builtin_popcountll(b2));
-        if (total == 0) return CODAG_E_CORRUPT;  // >= 253 continuation bytes
-        uint32_t use = min(total, count - done);
+        for (uint32_t j = 0; j < 6; j++) wd[j] = in.word(wb - 4 + j);  // bytes [at - 16, at + 8)
+        uint32_t tm = terminators4(wd[4]) | (terminators4(wd[5]) << 4);
+        if (at < pos) tm &= pos - at >= 8 ? 0u : (0xffu << (pos - at)) & 0xffu;
+        const uint32_t cnt = __builtin_popcount(tm);
+        const uint32_t incl = wave_inclusive_sum32(cnt);
+        const uint32_t total = readlane(incl, kWave - 1);
+        if (total == 0) return CODAG_E_CORRUPT;  // >= 505 continuation bytes
+        const uint32_t use = min(total, count - done);
+        // One past the last terminator of the lanes below (0: none).
+        const uint32_t after = tm ? at + (31 - __builtin_clz(tm)) + 1 : 0;
+        const uint32_t prev = wave_shift_up1(wave_inclusive_max32(after));
+        uint32_t s = max(prev, pos), g = incl - cnt, rem = tm, stop = 0;
+        int st = CODAG_OK;
+        while (ballot(rem != 0 && g < use)) {
+            if (rem != 0 && g < use) {
+                const uint32_t e = at + (uint32_t)__builtin_ctz(rem);  // terminator position
+                rem &= rem - 1;
+                const uint32_t nb = e - s + 1;
+                if (nb > 10) {
+                    if (st == CODAG_OK) st = CODAG_E_CORRUPT;
+                } else {
+                    // Bytes [s, e] from the register window: offset o in 7..23.
+                    const uint32_t o = s + 16 - at, wi = o >> 2, sh = o & 3;
+                    uint32_t v[4];
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-            if ((tm >> k) & 1) {
-                if (idx < use) ends[idx] = at + k;
-                idx++;
+                    for (uint32_t t = 0; t < 4; t++) {
+                        uint32_t k = wi + t, r = 0;
+#pragma unroll
+                        for (uint32_t j = 1; j < 6; j++) r = k == j ? wd[j] : r;
+                        v[t] = r;
+                    }
+                    const uint64_t x = ((uint64_t)__builtin_amdgcn_alignbyte(v[2], v[1], sh) << 32) |
+                                       __builtin_amdgcn_alignbyte(v[1], v[0], sh);
+                    const uint32_t y = __builtin_amdgcn_alignbyte(v[3], v[2], sh);
+                    const uint32_t b9 = (y >> 8) & 0xff;
+                    if (st == CODAG_OK) {
+                        if (e >= end) st = CODAG_E_TRUNCATED;
+                        else if (nb == 10 && b9 > 1) st = CODAG_E_CORRUPT;
+                    }
+                    uint64_t z = pack7(low_bytes(x, nb));
+                    if (nb > 8) z |= (uint64_t)(y & 0x7f) << 56;
+                    if (nb > 9) z |= (uint64_t)(b9 & 1) << 63;
+                    if (st == CODAG_OK) out[done + g] = unzigzag(z);
+                }
+                if (g == use - 1) stop = e + 1;
+                s = e + 1;
+                g++;
             }
         }
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int it = 0; it < 2; it++) {
-            uint32_t k = lane() + 64 * it;
-            int st = CODAG_OK;
-            if (k < use) {
-                uint32_t s = k ? ends[k - 1] + 1 : pos;
-                uint32_t e = ends[k];
-                uint32_t nb = e - s + 1;
-                uint64_t lo, hi;
-                ring_read16(in, s, lo, hi);
-                uint32_t b9 = (uint32_t)((hi >> 8) & 0xff);
-                if (nb > 10)
-                    st = CODAG_E_CORRUPT;
-                else if (e >= end)
-                    st = CODAG_E_TRUNCATED;
-                else if (nb == 10 && b9 > 1)
-                    st = CODAG_E_CORRUPT;
-                uint64_t z = pack7(low_bytes(lo, nb));
-                if (nb > 8) z |= (hi & 0x7f) << 56;
-                if (nb > 9) z |= (uint64_t)(b9 & 1) << 63;
-                if (st == CODAG_OK) out[done + k] = unzigzag(z);
-            }
-            uint64_t bad = ballot(st != CODAG_OK);
-            if (bad) return (int)uni((uint32_t)readlane((uint32_t)st, (uint32_t)__builtin_ctzll(bad)));
-        }
-        pos = uni(ends[use - 1]) + 1;
+        // The first failing varint in list order: lanes hold increasing
+        // indices, and each lane keeps its first failure.
+        const uint64_t bad = ballot(st != CODAG_OK);
+        if (bad) return (int)uni((uint32_t)readlane((uint32_t)st, (uint32_t)__builtin_ctzll(bad)));
+        pos = uni(readlane(stop, (uint32_t)__builtin_ctzll(ballot(stop != 0))));
         done += use;
     }
     return CODAG_OK;
@@ -125,23 +145,28 @@ __device__ __forceinline__ int rle_literal_list(InRing &in, uint32_t &pos, uint3
 // ---- RLE v1 ------------------------------------------------------------
 
 // Runs: header 0..127 = length - 3, a signed delta byte, a zigzag varint base.
-// Literal lists: header -1..-128 = -count, then count zigzag varints.
-__device__ __forceinline__ int decode_rle_v1(InRing &in, uint64_t *out, uint32_t cap, uint32_t *ends) {
+// Literal lists: header -1..-128 = -count, then count zigzag varints.  One
+// 16-byte read gives a run's header, delta and base together.
+__device__ __forceinline__ int decode_rle_v1(InRing &in, uint64_t *out, uint32_t cap) {
     uint32_t pos = in.skip, end = in.gend;
     uint32_t n = 0;
     while (n < cap) {
         if (pos >= end) return CODAG_E_TRUNCATED;
-        in.ensure(pos + 16);
-        uint64_t x = in.peek8(pos);
-        int32_t h = (int8_t)(x & 0xff);
+        in.ensure(pos + 24);
+        uint64_t lo, hi;
+        ring_read16(in, pos, lo, hi);
+        lo = uni64(lo);
+        int32_t h = (int8_t)(lo & 0xff);
         if (h >= 0) {
             uint32_t len = (uint32_t)h + 3;
             if (pos + 2 > end) return CODAG_E_TRUNCATED;
-            int32_t delta = (int8_t)((x >> 8) & 0xff);
-            pos += 2;
+            int32_t delta = (int8_t)((lo >> 8) & 0xff);
+            hi = uni64(hi);
             uint64_t z;
-            int st = read_varint(in, pos, end, z);
-            if (st) return st;
+            uint32_t nb = varint_bytes((lo >> 16) | (hi << 48), (uint32_t)(hi >> 16), z);
+            if (nb == 0) return CODAG_E_CORRUPT;
+            if (pos + 2 + nb > end) return CODAG_E_TRUNCATED;
+            pos += 2 + nb;
             if (n + len > cap) return CODAG_E_OVERFLOW;
             uint64_t base = unzigzag(z);
             for (uint32_t i = lane(); i < len; i += kWave)
@@ -151,7 +176,7 @@ __device__ __forceinline__ int decode_rle_v1(InRing &in, uint64_t *out, uint32_t
             uint32_t len = (uint32_t)(-h);
             pos += 1;
             if (n + len > cap) return CODAG_E_OVERFLOW;
-            int st = rle_literal_list(in, pos, end, len, out + n, ends);
+            int st = rle_literal_list(in, pos, end, len, out + n);
             if (st) return st;
             n += len;
         }
@@ -200,40 +225,51 @@ __device__ __forceinline__ void ensure_packed_batch(InRing &in, uint32_t sec, ui
 
 // A stretch of SHORT_REPEAT runs starting at pos.  Every lane decodes the
 // 64-byte window as if a SHORT_REPEAT header started at its own byte (width,
-// count and value from the following bytes); the wave then walks the chain of
-// runs from lane 0, pulling each run's fields out with readlane instead of a
-// round trip to LDS per run.  Stops at the first header that is not a
-// SHORT_REPEAT, past the window, at the end of input or when the output is
-// full, leaving pos at the next unread header.
+// count and value from the following bytes).  The wave then walks the chain
+// of runs from lane 0 with one lane read per run, marking the lanes where
+// runs start, and finally every marked lane writes its run at the position a
+// wave prefix sum of the run lengths gives it.  Stops at the first header
+// that is not a SHORT_REPEAT, past the window, at the end of input or when
+// the output is full, leaving pos at the next unread header.
 __device__ __forceinline__ int rle_v2_short_repeats(InRing &in, uint32_t &pos, uint32_t end,
                                                     uint64_t *out, uint32_t &n, uint32_t cap) {
+    const uint32_t l = lane();
     in.ensure(pos + 80);
     uint64_t lo, hi;
-    ring_read16(in, pos + lane(), lo, hi);
-    uint32_t h = (uint32_t)(lo & 0xff);
-    uint32_t w = ((h >> 3) & 7) + 1;
-    uint64_t vbytes = (lo >> 8) | (hi << 56);
-    uint64_t v = unzigzag(__builtin_bswap64(vbytes) >> (64 - 8 * w));
-    uint32_t s = 0;
-    int st = CODAG_OK;
-    while (s < 64 && pos + s < end) {
-        uint32_t hs = readlane(h, s);
-        if (hs >> 6) break;  // not a SHORT_REPEAT header
-        uint32_t ws = ((hs >> 3) & 7) + 1, cs = (hs & 7) + 3;
-        if (n + cs > cap) {
-            st = CODAG_E_OVERFLOW;
-            break;
-        }
-        if (pos + s + 1 + ws > end) {
-            st = CODAG_E_TRUNCATED;
-            break;
-        }
-        uint64_t vs = readlane64(v, s);
-        if (lane() < cs) out[n + lane()] = vs;
-        n += cs;
+    ring_read16(in, pos + l, lo, hi);
+    const uint32_t h = (uint32_t)(lo & 0xff);
+    const uint32_t w = ((h >> 3) & 7) + 1;
+    const uint64_t vbytes = (lo >> 8) | (hi << 56);
+    const uint64_t v = unzigzag(__builtin_bswap64(vbytes) >> (64 - 8 * w));
+    // Walk: integer flags keep the loop in scalar registers (values < 2^31).
+    uint32_t s = 0, m = n, bad;
+    uint64_t starts = 0;
+    for (;;) {
+        const uint32_t hs = readlane(h, s);
+        const uint32_t ws = ((hs >> 3) & 7) + 1, cs = (hs & 7) + 3;
+        bad = (hs >> 6) | (uint32_t)((int32_t)(cap - (m + cs)) >> 31) |
+              (uint32_t)((int32_t)(end - (pos + s + 1 + ws)) >> 31);
+        if (bad) break;
+        starts |= 1ull << s;
+        m += cs;
         s += 1 + ws;
-        if (n >= cap) break;
+        // Past the window, at the end of input, or the output full.
+        if ((s >> 6) | (uint32_t)(((int32_t)(pos + s - end) >> 31) + 1) |
+            (uint32_t)(((int32_t)(m - cap) >> 31) + 1))
+            break;
     }
+    int st = CODAG_OK;
+    if (bad) {
+        const uint32_t hs = readlane(h, s), ws = ((hs >> 3) & 7) + 1, cs = (hs & 7) + 3;
+        if ((hs >> 6) == 0) st = m + cs > cap ? CODAG_E_OVERFLOW : CODAG_E_TRUNCATED;
+    }
+    // The marked runs, lane-parallel.
+    const bool mine = (starts >> l) & 1;
+    const uint32_t c = mine ? (h & 7) + 3 : 0;
+    const uint32_t at = n + wave_inclusive_sum32(c) - c;
+    for (uint32_t j = 0; j < 10; j++)
+        if (j < c) out[at + j] = v;
+    n = m;
     pos += s;
     return st;
 }

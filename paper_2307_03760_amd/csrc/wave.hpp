@@ -46,6 +46,7 @@ enum : int {
     kDppRowShr8 = 0x118,
     kDppRowBcast15 = 0x142,
     kDppRowBcast31 = 0x143,
+    kDppWaveShr1 = 0x138,
 };
 
 template <int Ctrl, int RowMask>
@@ -81,6 +82,20 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum32(uint32_t x) {
     x += dpp32<kDppRowBcast31, 0xc>(x);
     return x;
 }
+
+// Inclusive running maximum over the 64 lanes; all lanes active.
+__device__ __forceinline__ uint32_t wave_inclusive_max32(uint32_t x) {
+    x = max(x, dpp32<kDppRowShr1, 0xf>(x));
+    x = max(x, dpp32<kDppRowShr2, 0xf>(x));
+    x = max(x, dpp32<kDppRowShr4, 0xf>(x));
+    x = max(x, dpp32<kDppRowShr8, 0xf>(x));
+    x = max(x, dpp32<kDppRowBcast15, 0xa>(x));
+    x = max(x, dpp32<kDppRowBcast31, 0xc>(x));
+    return x;
+}
+
+// The previous lane's value (0 on lane 0); all lanes active.
+__device__ __forceinline__ uint32_t wave_shift_up1(uint32_t x) { return dpp32<kDppWaveShr1, 0xf>(x); }
 
 __device__ __forceinline__ uint32_t bswap32(uint32_t x) { return __builtin_bswap32(x); }
 
