@@ -218,6 +218,10 @@ __device__ __forceinline__ uint64_t packed_value(const InRing &in, uint32_t sec,
     return ring_bits_msb(in, 8ull * sec + (uint64_t)i * w, w);
 }
 
+// A packed section this long (plus a few bytes of lookahead) is readable in
+// the ring at once.
+constexpr uint32_t kWholeSection = kFetchBytes - 32;
+
 __device__ __forceinline__ void ensure_packed_batch(InRing &in, uint32_t sec, uint32_t i0, uint32_t w) {
     uint64_t last_bit = (uint64_t)(i0 + kWave) * w;  // one past the batch's last bit
     in.ensure(sec + (uint32_t)((last_bit + 7) >> 3) + 12);
@@ -234,7 +238,7 @@ __device__ __forceinline__ void ensure_packed_batch(InRing &in, uint32_t sec, ui
 __device__ __forceinline__ int rle_v2_short_repeats(InRing &in, uint32_t &pos, uint32_t end,
                                                     uint64_t *out, uint32_t &n, uint32_t cap) {
     const uint32_t l = lane();
-    in.ensure(pos + 80);
+    in.ensure(pos + 84);
     uint64_t lo, hi;
     ring_read16(in, pos + l, lo, hi);
     const uint32_t h = (uint32_t)(lo & 0xff);
@@ -298,10 +302,21 @@ __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t
             if (n + len > cap) return CODAG_E_OVERFLOW;
             uint32_t sec = pos + 2, nbytes = (len * w + 7) >> 3;
             if (sec + nbytes > end) return CODAG_E_TRUNCATED;
-            for (uint32_t i0 = 0; i0 < len; i0 += kWave) {
-                ensure_packed_batch(in, sec, i0, w);
-                uint32_t i = i0 + l;
-                if (i < len) out[n + i] = unzigzag(packed_value(in, sec, i, w));
+            if (nbytes <= kWholeSection) {
+                // The whole section is readable at once: eight unrolled
+                // batches, so their LDS reads overlap.
+                in.ensure(sec + nbytes + 12);
+#pragma unroll
+                for (uint32_t b = 0; b < 8; b++) {
+                    uint32_t i = kWave * b + l;
+                    if (i < len) out[n + i] = unzigzag(packed_value(in, sec, i, w));
+                }
+            } else {
+                for (uint32_t i0 = 0; i0 < len; i0 += kWave) {
+                    ensure_packed_batch(in, sec, i0, w);
+                    uint32_t i = i0 + l;
+                    if (i < len) out[n + i] = unzigzag(packed_value(in, sec, i, w));
+                }
             }
             pos = sec + nbytes;
             n += len;
@@ -324,19 +339,28 @@ __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t
             if (dsec + dbytes > end) return CODAG_E_TRUNCATED;
             uint32_t psec = dsec + dbytes, pbytes = (pll * ew + 7) >> 3;
             if (psec + pbytes > end) return CODAG_E_TRUNCATED;
-            // Patch list: entry j on lane j, read straight from global memory.
+            // Patch list: entry j on lane j, from the ring when the data and
+            // the list fit in it together (no global load, whose wait would
+            // also wait for every store in flight), else from global memory.
             uint64_t gap = 0, patch = 0;
+            const bool whole = psec + pbytes - dsec <= kWholeSection;
+            if (whole) in.ensure(psec + pbytes + 12);
             if (l < pll) {
-                uint64_t bit = 8ull * psec + (uint64_t)l * ew;
-                uint32_t byte = (uint32_t)(bit >> 3), wi = byte >> 2;
-                uint32_t o = 8 * (byte & 3) + (uint32_t)(bit & 7);
-                const uint32_t *g = reinterpret_cast<const uint32_t *>(in.gbase);
-                uint32_t a = g[wi];
-                uint32_t b = 4 * (wi + 1) < end ? g[wi + 1] : 0;
-                uint32_t c = 4 * (wi + 2) < end ? g[wi + 2] : 0;
-                uint64_t hi = ((uint64_t)bswap32(a) << 32) | bswap32(b);
-                uint64_t top = o ? (hi << o) | ((uint64_t)bswap32(c) >> (32 - o)) : hi;
-                uint64_t e = ew >= 64 ? top : top >> (64 - ew);
+                uint64_t e;
+                if (whole) {
+                    e = ring_bits_msb(in, 8ull * psec + (uint64_t)l * ew, ew);
+                } else {
+                    uint64_t bit = 8ull * psec + (uint64_t)l * ew;
+                    uint32_t byte = (uint32_t)(bit >> 3), wi = byte >> 2;
+                    uint32_t o = 8 * (byte & 3) + (uint32_t)(bit & 7);
+                    const uint32_t *g = reinterpret_cast<const uint32_t *>(in.gbase);
+                    uint32_t a = g[wi];
+                    uint32_t b = 4 * (wi + 1) < end ? g[wi + 1] : 0;
+                    uint32_t c = 4 * (wi + 2) < end ? g[wi + 2] : 0;
+                    uint64_t hi = ((uint64_t)bswap32(a) << 32) | bswap32(b);
+                    uint64_t top = o ? (hi << o) | ((uint64_t)bswap32(c) >> (32 - o)) : hi;
+                    e = ew >= 64 ? top : top >> (64 - ew);
+                }
                 gap = e >> pw;
                 patch = pw >= 64 ? e : e & ((1ull << pw) - 1);
             }
@@ -345,7 +369,7 @@ __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t
             if (ballot(l < pll && !filler && cursor >= len)) return CODAG_E_CORRUPT;
             uint32_t jp = 0;
             for (uint32_t i0 = 0; i0 < len; i0 += kWave) {
-                ensure_packed_batch(in, dsec, i0, w);
+                if (!whole) ensure_packed_batch(in, dsec, i0, w);
                 uint32_t i = i0 + l;
                 uint64_t v = i < len ? packed_value(in, dsec, i, w) : 0;
                 while (jp < pll) {
@@ -367,10 +391,36 @@ __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t
             uint32_t w = code ? orc_width(code) : 0;
             uint32_t p = pos + 2;
             uint64_t zb, zd;
-            int st = read_varint(in, p, end, zb);
-            if (st) return st;
-            st = read_varint(in, p, end, zd);
-            if (st) return st;
+            {
+                // Both varints from one 32-byte read.
+                in.ensure(p + 36);
+                uint64_t a0, a1, a2, a3;
+                ring_read16(in, p, a0, a1);
+                ring_read16(in, p + 16, a2, a3);
+                a0 = uni64(a0);
+                a1 = uni64(a1);
+                a2 = uni64(a2);
+                uint32_t nb = varint_bytes(a0, (uint32_t)a1, zb);
+                if (nb == 0) return CODAG_E_CORRUPT;
+                if (p + nb > end) return CODAG_E_TRUNCATED;
+                // The second varint's bytes: ten from offset nb (1..10) of
+                // a0..a2, by byte alignment of the words around it.
+                const uint32_t d0 = (uint32_t)a0, d1 = (uint32_t)(a0 >> 32), d2 = (uint32_t)a1,
+                               d3 = (uint32_t)(a1 >> 32), d4 = (uint32_t)a2, d5 = (uint32_t)(a2 >> 32);
+                const uint32_t wi = nb >> 2, sb = nb & 3;
+                const uint32_t e0 = wi == 0 ? d0 : wi == 1 ? d1 : d2;
+                const uint32_t e1 = wi == 0 ? d1 : wi == 1 ? d2 : d3;
+                const uint32_t e2 = wi == 0 ? d2 : wi == 1 ? d3 : d4;
+                const uint32_t e3 = wi == 0 ? d3 : wi == 1 ? d4 : d5;
+                const uint64_t x = ((uint64_t)uni(__builtin_amdgcn_alignbyte(e2, e1, sb)) << 32) |
+                                   uni(__builtin_amdgcn_alignbyte(e1, e0, sb));
+                const uint32_t y = uni(__builtin_amdgcn_alignbyte(e3, e2, sb));
+                p += nb;
+                uint32_t nb2 = varint_bytes(x, y, zd);
+                if (nb2 == 0) return CODAG_E_CORRUPT;
+                if (p + nb2 > end) return CODAG_E_TRUNCATED;
+                p += nb2;
+            }
             if (n + len > cap) return CODAG_E_OVERFLOW;
             uint64_t base = unzigzag(zb), dbase = unzigzag(zd);
             if (w == 0) {
@@ -383,8 +433,10 @@ __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t
                 if (p + nbytes > end) return CODAG_E_TRUNCATED;
                 bool neg = (uint32_t)(dbase >> 63) != 0;
                 uint64_t prev = base + dbase;
+                const bool whole = nbytes <= kWholeSection;
+                if (whole) in.ensure(p + nbytes + 12);
                 for (uint32_t i0 = 0; i0 < nd; i0 += kWave) {
-                    ensure_packed_batch(in, p, i0, w);
+                    if (!whole) ensure_packed_batch(in, p, i0, w);
                     uint32_t i = i0 + l;
                     uint64_t d = i < nd ? packed_value(in, p, i, w) : 0;
                     uint64_t s = wave_inclusive_sum(d);

@@ -128,23 +128,15 @@ struct InRing {
 };
 
 // Sixteen bytes at position pos as little-endian (lo, hi) pairs, per lane
-// (needs the four words from pos >> 2 readable).
+// (needs the five words from pos >> 2 readable).
 __device__ __forceinline__ void ring_read16(const InRing &in, uint32_t pos, uint64_t &lo, uint64_t &hi) {
-    uint32_t w = pos >> 2;
-    uint32_t a = in.word_at(w, 0), b = in.word_at(w, 1), c = in.word_at(w, 2), d = in.word_at(w, 3);
-    uint32_t sh = 8 * (pos & 3);
-    uint64_t x0 = ((uint64_t)b << 32) | a, x1 = ((uint64_t)d << 32) | c;
-    if (sh) {
-        lo = (x0 >> sh) | (x1 << (64 - sh));
-        hi = x1 >> sh;
-    } else {
-        lo = x0;
-        hi = x1;
-    }
+    const uint32_t w = pos >> 2, sh = 8 * (pos & 3);
+    const uint32_t a = in.word_at(w, 0), b = in.word_at(w, 1), c = in.word_at(w, 2),
+                   d = in.word_at(w, 3), e = in.word_at(w, 4);
+    lo = ((uint64_t)__builtin_amdgcn_alignbit(c, b, sh) << 32) | __builtin_amdgcn_alignbit(b, a, sh);
+    hi = ((uint64_t)__builtin_amdgcn_alignbit(e, d, sh) << 32) | __builtin_amdgcn_alignbit(d, c, sh);
 }
 
-// W bits (1..64) most significant first, starting `bit` bits into the byte
-// stream at byte position 0 of the ring's coordinates (per lane).
 __device__ __forceinline__ uint64_t ring_bits_msb(const InRing &in, uint64_t bit, uint32_t w) {
     uint32_t byte = (uint32_t)(bit >> 3);
     uint32_t wi = byte >> 2;
