@@ -55,13 +55,22 @@ enum {
  *                     With 32 the workgroup holds one wave.
  *   chunk_ticks       optional device array (n_chunks uint64): receives each
  *                     chunk's decode time in shader clock cycles.
+ *   group_parallel    RLE v1 only: 0 = automatic (launches of at most 256
+ *                     chunks without chunk_ticks are decoded group-parallel:
+ *                     an index pass records where each run or literal list
+ *                     starts, then 16 waves per chunk decode them), 1 = one
+ *                     wave per chunk, 2 = group-parallel (not with
+ *                     chunk_ticks).  The group-parallel path takes its
+ *                     workspace (16 KiB per chunk) from the stream-ordered
+ *                     allocator (hipMallocAsync) on `stream`.
  */
 typedef struct codag_opts {
     int waves_per_block;
     int lit_table_bits;
     uint64_t *chunk_ticks;
     int history_kib;
-    int reserved[7];
+    int group_parallel;
+    int reserved[6];
 } codag_opts;
 
 /*

@@ -33,7 +33,7 @@ class CodagError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_int), ("lit_table_bits", ctypes.c_int),
                 ("chunk_ticks", ctypes.c_void_p), ("history_kib", ctypes.c_int),
-                ("reserved", ctypes.c_int * 7)]
+                ("group_parallel", ctypes.c_int), ("reserved", ctypes.c_int * 6)]
 
 
 class BatchOpts(ctypes.Structure):
@@ -118,7 +118,7 @@ def _check_dev(t, name, dtype=None, n=None):
 
 def decompress(codec: int, comp, chunk_offsets, out, out_offsets, *, status=None,
                waves_per_block: int = 0, lit_table_bits: int = 0, history_kib: int = 0,
-               chunk_ticks=None, stream=None) -> None:
+               group_parallel: int = 0, chunk_ticks=None, stream=None) -> None:
     """Enqueue codag_decompress_ex on `stream` (default: torch's current stream).
 
     comp: uint8 device tensor; chunk_offsets/out_offsets: int64 device tensors of
@@ -136,7 +136,7 @@ def decompress(codec: int, comp, chunk_offsets, out, out_offsets, *, status=None
     d = _check_dev(out_offsets, "out_offsets", offs)
     s = _check_dev(status, "status", (torch.int32,), n)
     t = _check_dev(chunk_ticks, "chunk_ticks", (torch.int64,), n)
-    opts = Opts(waves_per_block, lit_table_bits, t, history_kib, (ctypes.c_int * 7)())
+    opts = Opts(waves_per_block, lit_table_bits, t, history_kib, group_parallel, (ctypes.c_int * 6)())
     rc = lib().codag_decompress_ex(int(codec), a, b, c, d, n, _stream_handle(stream), s,
                                    ctypes.byref(opts))
     if rc != OK:

@@ -130,6 +130,8 @@ int codag_decompress_ex(int codec, const uint8_t *comp_buf, const uint64_t *chun
     int wpb = opts && opts->waves_per_block ? opts->waves_per_block : codec == CODAG_DEFLATE ? 1 : 4;
     int tb = opts && opts->lit_table_bits ? opts->lit_table_bits : 9;
     int hist = opts && opts->history_kib ? opts->history_kib : 4;
+    if (opts && (opts->group_parallel < 0 || opts->group_parallel > 2)) return CODAG_E_INVALID_ARGUMENT;
+    if (opts && opts->group_parallel == 2 && opts->chunk_ticks) return CODAG_E_INVALID_ARGUMENT;
     if ((wpb != 1 && wpb != 2 && wpb != 4) || (tb != 9 && tb != 10) ||
         (hist != 2 && hist != 4 && hist != 8 && hist != 16 && hist != 32))
         return CODAG_E_INVALID_ARGUMENT;
@@ -139,7 +141,12 @@ int codag_decompress_ex(int codec, const uint8_t *comp_buf, const uint64_t *chun
     if (st) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     switch (codec) {
-        case CODAG_RLE_V1:
+        case CODAG_RLE_V1: {
+            const int gp = opts ? opts->group_parallel : 0;
+            if (gp == 2 || (gp == 0 && !ticks && n_chunks <= kSplitMaxChunks))
+                return launch_rle_v1_split(comp_buf, chunk_offsets, out_buf, out_offsets,
+                                           (uint32_t)n_chunks, chunk_status, ds->err, s);
+        }
             return launch_plain<CODAG_RLE_V1, 10, 0>(comp_buf, chunk_offsets, out_buf, out_offsets,
                                                      n_chunks, wpb, chunk_status, ds->err, ticks, s);
         case CODAG_RLE_V2:

@@ -23,6 +23,12 @@ extern DeviceState g_dev[kMaxDevices];
 // The current device's state, created on first use.
 int device_state(DeviceState **out);
 
+// Group-parallel RLE v1 (few chunks): index, decode and status passes on s.
+int launch_rle_v1_split(const uint8_t *comp, const uint64_t *coff, uint8_t *out,
+                        const uint64_t *ooff, uint32_t n, int32_t *status, unsigned long long *err,
+                        hipStream_t s);
+constexpr uint64_t kSplitMaxChunks = 256;
+
 // Arguments of one batched launch (a captured graph is reused while they
 // stay the same).
 struct BatchArgs {

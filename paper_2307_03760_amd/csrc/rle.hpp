@@ -144,44 +144,85 @@ __device__ __forceinline__ int rle_literal_list(InRing &in, uint32_t &pos, uint3
 
 // ---- RLE v1 ------------------------------------------------------------
 
-// Runs: header 0..127 = length - 3, a signed delta byte, a zigzag varint base.
-// Literal lists: header -1..-128 = -count, then count zigzag varints.  One
-// 16-byte read gives a run's header, delta and base together.
+// One group at pos, whose first value is value n of the chunk.  Runs: header
+// 0..127 = length - 3, a signed delta byte, a zigzag varint base.  Literal
+// lists: header -1..-128 = -count, then count zigzag varints.  One 16-byte
+// read gives a run's header, delta and base together.  Advances pos and n.
+__device__ __forceinline__ int rle_v1_group(InRing &in, uint32_t &pos, uint32_t end, uint64_t *out,
+                                            uint32_t &n, uint32_t cap) {
+    if (pos >= end) return CODAG_E_TRUNCATED;
+    in.ensure(pos + 24);
+    uint64_t lo, hi;
+    ring_read16(in, pos, lo, hi);
+    lo = uni64(lo);
+    int32_t h = (int8_t)(lo & 0xff);
+    if (h >= 0) {
+        uint32_t len = (uint32_t)h + 3;
+        if (pos + 2 > end) return CODAG_E_TRUNCATED;
+        int32_t delta = (int8_t)((lo >> 8) & 0xff);
+        hi = uni64(hi);
+        uint64_t z;
+        uint32_t nb = varint_bytes((lo >> 16) | (hi << 48), (uint32_t)(hi >> 16), z);
+        if (nb == 0) return CODAG_E_CORRUPT;
+        if (pos + 2 + nb > end) return CODAG_E_TRUNCATED;
+        pos += 2 + nb;
+        if (n + len > cap) return CODAG_E_OVERFLOW;
+        uint64_t base = unzigzag(z);
+        for (uint32_t i = lane(); i < len; i += kWave)
+            out[n + i] = base + (uint64_t)(int64_t)((int32_t)i * delta);
+        n += len;
+        return CODAG_OK;
+    }
+    uint32_t len = (uint32_t)(-h);
+    pos += 1;
+    if (n + len > cap) return CODAG_E_OVERFLOW;
+    int st = rle_literal_list(in, pos, end, len, out + n);
+    if (st) return st;
+    n += len;
+    return CODAG_OK;
+}
+
 __device__ __forceinline__ int decode_rle_v1(InRing &in, uint64_t *out, uint32_t cap) {
     uint32_t pos = in.skip, end = in.gend;
     uint32_t n = 0;
     while (n < cap) {
-        if (pos >= end) return CODAG_E_TRUNCATED;
-        in.ensure(pos + 24);
-        uint64_t lo, hi;
-        ring_read16(in, pos, lo, hi);
-        lo = uni64(lo);
-        int32_t h = (int8_t)(lo & 0xff);
-        if (h >= 0) {
-            uint32_t len = (uint32_t)h + 3;
-            if (pos + 2 > end) return CODAG_E_TRUNCATED;
-            int32_t delta = (int8_t)((lo >> 8) & 0xff);
-            hi = uni64(hi);
-            uint64_t z;
-            uint32_t nb = varint_bytes((lo >> 16) | (hi << 48), (uint32_t)(hi >> 16), z);
-            if (nb == 0) return CODAG_E_CORRUPT;
-            if (pos + 2 + nb > end) return CODAG_E_TRUNCATED;
-            pos += 2 + nb;
-            if (n + len > cap) return CODAG_E_OVERFLOW;
-            uint64_t base = unzigzag(z);
-            for (uint32_t i = lane(); i < len; i += kWave)
-                out[n + i] = base + (uint64_t)(int64_t)((int32_t)i * delta);
-            n += len;
-        } else {
-            uint32_t len = (uint32_t)(-h);
-            pos += 1;
-            if (n + len > cap) return CODAG_E_OVERFLOW;
-            int st = rle_literal_list(in, pos, end, len, out + n);
-            if (st) return st;
-            n += len;
-        }
+        int st = rle_v1_group(in, pos, end, out, n, cap);
+        if (st) return st;
     }
     return pos == end ? CODAG_OK : CODAG_E_CORRUPT;
+}
+
+// Position just past the `count`-th varint terminator at or after pos
+// (a literal list's end), counting 512 bytes per pass.  Returns 0 if the
+// list does not end inside the chunk (a terminator at or past `end`, or a
+// pass without terminators): the list is then malformed.
+__device__ __forceinline__ uint32_t rle_skip_varints(InRing &in, uint32_t pos, uint32_t end,
+                                                     uint32_t count) {
+    const uint32_t l = lane();
+    uint32_t need = count;
+    for (;;) {
+        const uint32_t p0 = pos & ~7u;
+        in.ensure(p0 + 528);
+        const uint32_t at = p0 + 8 * l, wb = at >> 2;
+        uint32_t tm = terminators4(in.word(wb)) | (terminators4(in.word(wb + 1)) << 4);
+        if (at < pos) tm &= pos - at >= 8 ? 0u : (0xffu << (pos - at)) & 0xffu;
+        const uint32_t cnt = __builtin_popcount(tm);
+        const uint32_t incl = wave_inclusive_sum32(cnt);
+        const uint32_t total = readlane(incl, kWave - 1);
+        if (total == 0) return 0;
+        if (total < need) {
+            need -= total;
+            pos = p0 + 512;
+            if (pos >= end) return 0;
+            continue;
+        }
+        // The lane holding terminator number `need`, and its bit.
+        const uint32_t k = (uint32_t)__builtin_ctzll(ballot(incl >= need));
+        uint32_t m = readlane(tm, k), r = need - (readlane(incl, k) - readlane(cnt, k));
+        while (--r) m &= m - 1;
+        const uint32_t e = p0 + 8 * k + (uint32_t)__builtin_ctz(m);
+        return e >= end ? 0 : e + 1;
+    }
 }
 
 // ---- RLE v2 ------------------------------------------------------------

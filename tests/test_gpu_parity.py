@@ -41,6 +41,13 @@ def _chunks(codec, blobs, sizes):
 # ---- small workloads: several chunks and a ragged tail ---------------------
 
 @pytest.mark.parametrize("wpb", [1, 2, 4])
+def test_rle_v1_small_one_wave(dev, wpb):
+    ch = workloads.rle_v1_workload(seed=5, n_values=100_003, chunk_values=16384)
+    _say(f"rle_v1 small one wave per chunk wpb={wpb} chunks={ch.n_chunks}")
+    assert (assert_parity(oracle.RLE_V1, ch, dev, waves_per_block=wpb, group_parallel=1) == 0).all()
+
+
+@pytest.mark.parametrize("wpb", [1, 4])
 def test_rle_v1_small(dev, wpb):
     ch = workloads.rle_v1_workload(seed=5, n_values=100_003, chunk_values=16384)
     _say(f"rle_v1 small wpb={wpb} chunks={ch.n_chunks}")
@@ -100,11 +107,16 @@ def test_rle_extremes(dev):
     vals = [np.array([I64_MIN, I64_MAX, 0, -1, 1] * 40, dtype=np.int64),
             np.arange(1000, dtype=np.int64) * -128,
             (np.uint64(I64_MAX - 200) + np.arange(500, dtype=np.uint64)).view(np.int64),
-            np.random.default_rng(3).integers(I64_MIN, I64_MAX, 777, dtype=np.int64)]
-    for codec, encode in ((oracle.RLE_V1, enc.encode_rle_v1), (oracle.RLE_V2, enc.encode_rle_v2)):
+            np.random.default_rng(3).integers(I64_MIN, I64_MAX, 777, dtype=np.int64),
+            # 4,000 groups in one chunk (a run of three and a one-value list, repeated):
+            # more groups than the group-parallel index keeps per chunk.
+            np.column_stack([np.repeat(np.random.default_rng(4).integers(-9999, 9999, 2000), 3).reshape(-1, 3),
+                             np.random.default_rng(5).integers(I64_MIN, I64_MAX, 2000)]).reshape(-1)]
+    for codec, encode, gp in ((oracle.RLE_V1, enc.encode_rle_v1, 1), (oracle.RLE_V1, enc.encode_rle_v1, 2),
+                              (oracle.RLE_V2, enc.encode_rle_v2, 0)):
         ch = _chunks(codec, [encode(v) for v in vals], [8 * v.size for v in vals])
-        _say(f"rle extremes codec={codec}")
-        assert (assert_parity(codec, ch, dev) == 0).all()
+        _say(f"rle extremes codec={codec} group_parallel={gp}")
+        assert (assert_parity(codec, ch, dev, group_parallel=gp) == 0).all()
 
 
 def test_deflate_strategies_and_levels(dev):
@@ -179,10 +191,11 @@ def test_rle_output_rules(dev):
 def test_capacity_statuses(dev):
     vals = np.arange(200, dtype=np.int64) * 7
     blobs, sizes = [], []
-    for codec, encode in ((oracle.RLE_V1, enc.encode_rle_v1), (oracle.RLE_V2, enc.encode_rle_v2)):
+    for codec, encode, gp in ((oracle.RLE_V1, enc.encode_rle_v1, 1), (oracle.RLE_V1, enc.encode_rle_v1, 2),
+                              (oracle.RLE_V2, enc.encode_rle_v2, 0)):
         data = encode(vals)
         ch = _chunks(codec, [data, data, data, data + b"\x00", data[:-1]], [1600, 1592, 1608, 1600, 1600])
-        st = assert_parity(codec, ch, dev)
+        st = assert_parity(codec, ch, dev, group_parallel=gp)
         assert st.tolist() == [0, oracle.E_OVERFLOW, oracle.E_TRUNCATED, oracle.E_CORRUPT, oracle.E_TRUNCATED]
     d = workloads.zipf_text(30000, np.random.default_rng(2), workloads._vocab(0))
     z = workloads.deflate_raw(d)
@@ -208,8 +221,9 @@ def _mutants(blobs, rng, count):
     return out
 
 
-@pytest.mark.parametrize("codec", [oracle.RLE_V1, oracle.RLE_V2, oracle.DEFLATE])
-def test_corrupt_streams_status_parity(dev, codec):
+@pytest.mark.parametrize("codec,gp", [(oracle.RLE_V1, 1), (oracle.RLE_V1, 2), (oracle.RLE_V2, 0),
+                                      (oracle.DEFLATE, 0)])
+def test_corrupt_streams_status_parity(dev, codec, gp):
     rng = np.random.default_rng(100 + codec)
     if codec == oracle.DEFLATE:
         vocab = workloads._vocab(0)
@@ -225,17 +239,18 @@ def test_corrupt_streams_status_parity(dev, codec):
         sizes = [16000] * 3
     muts = _mutants(base, rng, 600)
     ch = _chunks(codec, muts, [sizes[t % len(sizes)] for t in range(len(muts))])
-    _say(f"corrupt codec={codec} chunks={ch.n_chunks}")
-    st = assert_parity(codec, ch, dev)
+    _say(f"corrupt codec={codec} group_parallel={gp} chunks={ch.n_chunks}")
+    st = assert_parity(codec, ch, dev, group_parallel=gp)
     assert (st != 0).sum() > 100
 
 
 # ---- full workload sizes, benchmark launch configuration ---------------------
 
-def test_full_rle_v1(dev):
+@pytest.mark.parametrize("gp", [0, 1])
+def test_full_rle_v1(dev, gp):
     ch = workloads.rle_v1_workload(seed=0)
-    _say(f"full rle_v1 chunks={ch.n_chunks}")
-    assert (assert_parity(oracle.RLE_V1, ch, dev) == 0).all()
+    _say(f"full rle_v1 chunks={ch.n_chunks} group_parallel={gp}")
+    assert (assert_parity(oracle.RLE_V1, ch, dev, group_parallel=gp) == 0).all()
 
 
 def test_full_rle_v2(dev):
