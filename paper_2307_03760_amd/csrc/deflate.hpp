@@ -523,7 +523,6 @@ __device__ __forceinline__ int inflate_symbols(InRing &in, BitIn &bi, WindowOut<
 // ---------------------------------------------------------------------------
 
 constexpr uint32_t kBatchOut = 1024;
-enum : uint32_t { kTokLit = 0, kTokMatch = 1, kTokEob = 2, kTokOther = 3 };
 
 // Length and distance bases and extra-bit counts (RFC 1951 section 3.2.5)
 // in closed form.
@@ -538,11 +537,17 @@ __device__ __forceinline__ uint32_t dist_base(uint32_t d) {
     return d < 4 ? d + 1 : ((2 + (d & 1)) << ((d >> 1) - 1)) + 1;
 }
 
-// The token starting at bit b + lane (b + 63 at most): info = bits used |
-// kind << 6 | (literal byte or match length) << 8, and a match's distance.
-// The lane's 64 input bits come from the wave-uniform words s0..s4 (input
-// words b/32 .. b/32 + 4); a length code with its extra bits, the distance
-// code and its extra bits take at most 36 bits.
+// Token words: a literal is 1 << 16 | byte, a copy is length << 16 | 0x8000;
+// bits 8-13 hold the bits the token takes in the input; 0x4000 marks a
+// token the batch cannot take (0x4000: end of block, 0xc000: anything that
+// needs the symbol-at-a-time path).
+constexpr uint32_t kTokCopy = 0x8000u, kTokStop = 0x4000u, kTokOther = 0xc000u;
+
+// The token starting at bit b + lane (b + 63 at most), as a token word, and
+// a copy's distance (0 otherwise).  The lane's 64 input bits come from the
+// wave-uniform words s0..s4 (input words b/32 .. b/32 + 4); a length code
+// with its extra bits, the distance code and its extra bits take at most 36
+// bits.
 template <int TB, uint32_t H>
 __device__ __forceinline__ void lane_token(uint32_t s0, uint32_t s1, uint32_t s2, uint32_t s3,
                                            uint32_t s4, uint32_t b, const DeflateLds<TB, H> *lds,
@@ -556,12 +561,12 @@ __device__ __forceinline__ void lane_token(uint32_t s0, uint32_t s1, uint32_t s2
                        __builtin_amdgcn_alignbit(wb, wa, sh);
     const uint32_t e = lds->lit[(uint32_t)x & ((1u << TB) - 1)];
     const uint32_t kind = e >> 13, cl = e & 15, sym = (e >> 4) & 511;
-    info = kTokOther << 6;
+    info = kTokOther;
     dist = 0;
     if (kind == kLit) {
-        info = cl | (kTokLit << 6) | (sym << 8);
+        info = (1u << 16) | (cl << 8) | sym;
     } else if (kind == kEob) {
-        info = cl | (kTokEob << 6);
+        info = kTokStop | (cl << 8);
     } else if (kind == kBase && have_dist) {
         const uint32_t kk = sym - 257, ex = length_extra(kk);
         const uint32_t len = length_base(kk) + ((uint32_t)(x >> cl) & ((1u << ex) - 1));
@@ -570,7 +575,7 @@ __device__ __forceinline__ void lane_token(uint32_t s0, uint32_t s1, uint32_t s2
         if ((d >> 13) == kBase) {
             const uint32_t dcl = d & 15, ds = (d >> 4) & 31, dex = dist_extra(ds);
             dist = dist_base(ds) + ((uint32_t)(x >> (p2 + dcl)) & ((1u << dex) - 1));
-            info = (p2 + dcl + dex) | (kTokMatch << 6) | (len << 8);
+            info = (len << 16) | kTokCopy | ((p2 + dcl + dex) << 8);
         }
     }
 }
@@ -591,6 +596,7 @@ __device__ __forceinline__ int inflate_batched(InRing &in, BitIn &bi, WindowOut<
         uint32_t tok = 0, tdist = 0;  // token k in lane k: length << 16 | literal, flag 0x8000 = copy
         uint32_t stop = 0;            // 1 full, 2 end of block, 3 one symbol the slow way
         const uint32_t total0 = o.pos;
+        uint32_t tpos = 0;  // token k's bit position, in lane k
         do {
             const uint32_t wi = p >> 5;
             if (wi + 5 > cend) {
@@ -603,32 +609,26 @@ __device__ __forceinline__ int inflate_batched(InRing &in, BitIn &bi, WindowOut<
             lane_token<TB, H>(readlane(cache, c0), readlane(cache, c0 + 1), readlane(cache, c0 + 2),
                               readlane(cache, c0 + 3), readlane(cache, c0 + 4), p, lds, have_dist,
                               info, dist);
-            // The walk from offset 0 has two exits: a token it cannot take
-            // here, and the end of the window or of the batch.  Flags are
-            // computed with integer arithmetic rather than comparisons, so the
-            // loop stays in scalar registers (all values are below 2^31).
-            uint32_t t = 0, inf, bad;
+            // The walk only follows token starts and collects tokens; output
+            // bounds are checked lane-parallel once the batch is complete.
+            // Exits: a token the batch cannot take, the end of the window,
+            // a full batch (flags by integer arithmetic: values < 2^31).
+            uint32_t t = 0, inf;
             for (;;) {
                 inf = readlane(info, t);
-                const uint32_t d = readlane(dist, t);  // 0 unless a copy
-                const uint32_t kind = (inf >> 6) & 3, v = inf >> 8;
-                const uint32_t m = 0u - (kind & 1);  // all ones for a copy
-                const uint32_t total = total0 + bout;
-                const uint32_t len = 1 + ((v - 1) & m);
-                bad = (kind >> 1) | (uint32_t)((int32_t)(o.cap - (total + len)) >> 31) |
-                      (uint32_t)((int32_t)(total - d) >> 31);
-                if (bad) break;
-                const uint32_t tv = (len << 16) | (v ^ ((v ^ 0x8000u) & m));
-                tok = l == ntok ? tv : tok;
+                if (inf & kTokStop) break;
+                const uint32_t d = readlane(dist, t);
+                tok = l == ntok ? inf : tok;
                 tdist = l == ntok ? d : tdist;
-                t += inf & 63;
+                tpos = l == ntok ? p + t : tpos;
+                t += (inf >> 8) & 63;
                 ntok++;
-                bout += len;
+                bout += inf >> 16;
                 if ((t >> 6) | (ntok >> 6) | (uint32_t)((int32_t)(kBatchOut - 258 - bout) >> 31)) break;
             }
-            if (bad) {
-                if (((inf >> 6) & 3) == kTokEob) {
-                    t += inf & 63;
+            if (inf & kTokStop) {
+                if (inf == (kTokStop | (inf & 0x3f00))) {  // end of block
+                    t += (inf >> 8) & 63;
                     stop = 2;
                 } else {
                     stop = 3;
@@ -638,6 +638,21 @@ __device__ __forceinline__ int inflate_batched(InRing &in, BitIn &bi, WindowOut<
             }
             p += t;
         } while (stop == 0);
+        // Output bounds, lane-parallel: the first token whose distance
+        // reaches before the chunk or whose output would pass the end ends
+        // the batch, and goes through the symbol-at-a-time path.
+        if (ntok) {
+            const uint32_t vlen = l < ntok ? tok >> 16 : 0;
+            const uint32_t before = total0 + wave_inclusive_sum32(vlen) - vlen;
+            const uint64_t badm = ballot(l < ntok && (tdist > before || before + vlen > o.cap));
+            if (badm) {
+                const uint32_t j = (uint32_t)__builtin_ctzll(badm);
+                ntok = j;
+                bout = readlane(before, j) - total0;
+                p = readlane(tpos, j);
+                stop = 3;
+            }
+        }
 
         // ---- write the batch
         if (ntok) {
