@@ -57,12 +57,13 @@ enum {
  *                     chunk's decode time in shader clock cycles.
  *   group_parallel    RLE v1 only: 0 = automatic (launches of at most 256
  *                     chunks without chunk_ticks are decoded group-parallel:
- *                     an index pass records where each run or literal list
- *                     starts, then 16 waves per chunk decode them), 1 = one
+ *                     an index pass walks the runs and literal lists and
+ *                     cuts them into 16 ranges of about equal output, then
+ *                     16 waves per chunk decode one range each), 1 = one
  *                     wave per chunk, 2 = group-parallel (not with
  *                     chunk_ticks).  The group-parallel path takes its
- *                     workspace (16 KiB per chunk) from the stream-ordered
- *                     allocator (hipMallocAsync) on `stream`.
+ *                     workspace (272 bytes per chunk) from the
+ *                     stream-ordered allocator (hipMallocAsync) on `stream`.
  */
 typedef struct codag_opts {
     int waves_per_block;

@@ -49,7 +49,8 @@ __device__ __forceinline__ uint32_t varint_bytes(uint64_t x, uint32_t y, uint64_
 }
 
 // Unsigned base-128 varint at byte position pos (wave-uniform).
-__device__ __forceinline__ int read_varint(InRing &in, uint32_t &pos, uint32_t end, uint64_t &z) {
+template <class Ring>
+__device__ __forceinline__ int read_varint(Ring &in, uint32_t &pos, uint32_t end, uint64_t &z) {
     in.ensure(pos + 24);
     uint64_t lo, hi;
     ring_read16(in, pos, lo, hi);
@@ -73,7 +74,8 @@ __device__ __forceinline__ uint32_t terminators4(uint32_t w) {
 // the last terminator of the lanes below, and then every lane decodes, from
 // its registers, the varints whose terminators it holds and stores them at
 // their index -- no compaction through LDS.
-__device__ __forceinline__ int rle_literal_list(InRing &in, uint32_t &pos, uint32_t end,
+template <class Ring>
+__device__ __forceinline__ int rle_literal_list(Ring &in, uint32_t &pos, uint32_t end,
                                                 uint32_t count, uint64_t *out) {
     const uint32_t l = lane();
     uint32_t done = 0;
@@ -148,7 +150,8 @@ __device__ __forceinline__ int rle_literal_list(InRing &in, uint32_t &pos, uint3
 // 0..127 = length - 3, a signed delta byte, a zigzag varint base.  Literal
 // lists: header -1..-128 = -count, then count zigzag varints.  One 16-byte
 // read gives a run's header, delta and base together.  Advances pos and n.
-__device__ __forceinline__ int rle_v1_group(InRing &in, uint32_t &pos, uint32_t end, uint64_t *out,
+template <class Ring>
+__device__ __forceinline__ int rle_v1_group(Ring &in, uint32_t &pos, uint32_t end, uint64_t *out,
                                             uint32_t &n, uint32_t cap) {
     if (pos >= end) return CODAG_E_TRUNCATED;
     in.ensure(pos + 24);
@@ -182,7 +185,8 @@ __device__ __forceinline__ int rle_v1_group(InRing &in, uint32_t &pos, uint32_t 
     return CODAG_OK;
 }
 
-__device__ __forceinline__ int decode_rle_v1(InRing &in, uint64_t *out, uint32_t cap) {
+template <class Ring>
+__device__ __forceinline__ int decode_rle_v1(Ring &in, uint64_t *out, uint32_t cap) {
     uint32_t pos = in.skip, end = in.gend;
     uint32_t n = 0;
     while (n < cap) {
@@ -190,39 +194,6 @@ __device__ __forceinline__ int decode_rle_v1(InRing &in, uint64_t *out, uint32_t
         if (st) return st;
     }
     return pos == end ? CODAG_OK : CODAG_E_CORRUPT;
-}
-
-// Position just past the `count`-th varint terminator at or after pos
-// (a literal list's end), counting 512 bytes per pass.  Returns 0 if the
-// list does not end inside the chunk (a terminator at or past `end`, or a
-// pass without terminators): the list is then malformed.
-__device__ __forceinline__ uint32_t rle_skip_varints(InRing &in, uint32_t pos, uint32_t end,
-                                                     uint32_t count) {
-    const uint32_t l = lane();
-    uint32_t need = count;
-    for (;;) {
-        const uint32_t p0 = pos & ~7u;
-        in.ensure(p0 + 528);
-        const uint32_t at = p0 + 8 * l, wb = at >> 2;
-        uint32_t tm = terminators4(in.word(wb)) | (terminators4(in.word(wb + 1)) << 4);
-        if (at < pos) tm &= pos - at >= 8 ? 0u : (0xffu << (pos - at)) & 0xffu;
-        const uint32_t cnt = __builtin_popcount(tm);
-        const uint32_t incl = wave_inclusive_sum32(cnt);
-        const uint32_t total = readlane(incl, kWave - 1);
-        if (total == 0) return 0;
-        if (total < need) {
-            need -= total;
-            pos = p0 + 512;
-            if (pos >= end) return 0;
-            continue;
-        }
-        // The lane holding terminator number `need`, and its bit.
-        const uint32_t k = (uint32_t)__builtin_ctzll(ballot(incl >= need));
-        uint32_t m = readlane(tm, k), r = need - (readlane(incl, k) - readlane(cnt, k));
-        while (--r) m &= m - 1;
-        const uint32_t e = p0 + 8 * k + (uint32_t)__builtin_ctz(m);
-        return e >= end ? 0 : e + 1;
-    }
 }
 
 // ---- RLE v2 ------------------------------------------------------------

@@ -4,12 +4,13 @@
 // SIMDs busy and each wave's decode is a long chain of dependent steps.
 // Here the chunk is decoded in two passes: an index pass (one wave per
 // chunk) walks the group headers -- runs fully, literal lists by counting
-// varint terminators without decoding them -- and records where every
-// group starts in the input and in the output; then kSplitWaves waves per
-// chunk decode the groups in parallel, each from its own input ring.  A
-// last pass combines, per chunk, the first error either pass saw (errors are
-// keyed by group index, so the earliest group wins, as in a sequential
-// decode).
+// varint terminators without decoding them -- and cuts the groups into
+// kSplitWaves ranges of about equal output, recording where each range
+// starts in the input and in the output; then kSplitWaves waves per chunk
+// decode the ranges in parallel, each streaming through its own part of the
+// input.  A last pass combines, per chunk, the first error either pass saw
+// (errors are keyed by group index, so the earliest group wins, as in a
+// sequential decode).
 #include <hip/hip_runtime.h>
 
 #include "../../include/codag.h"
@@ -18,69 +19,125 @@
 
 namespace codag {
 
-constexpr uint32_t kSplitGroups = 2048;      // group descriptors kept per chunk
-constexpr uint32_t kSplitWaves = 16;         // decoding waves per chunk
-constexpr uint32_t kSplitWholeChunk = ~0u;   // count: too many groups, one wave decodes the chunk
-constexpr int kSplitWpb = 4;
+constexpr uint32_t kSplitWaves = 16;  // decoding waves per chunk
+constexpr int kSplitWpb = 4;          // decode pass: waves per block
 
-// Index pass.  desc[c * kSplitGroups + k] = (input position, first value) of
-// group k of chunk c; count[c] = number of groups recorded; keys[2c] = the
-// first structural error (group << 4 | -status), or all ones.
-__global__ void __launch_bounds__(kWave * kSplitWpb)
+// With a few dozen waves on the chip each wave waits on every fetch it
+// makes, so the passes read their input in larger pieces than the one-wave
+// decoder: the index pass 8 KiB at a time (a chunk is a few dozen KiB), the
+// decode waves 4 KiB (each decodes a few KiB).
+using IndexRing = InRingT<8192>;
+using GroupRing = InRingT<4096>;
+
+// The index pass's view of the input: 512 bytes starting at w (8-aligned),
+// 8 per lane in registers.  Varint terminators (bytes with bit 7 clear) are
+// counted, per lane, as running counts in the bytes of c0 (bytes 0-3) and c1
+// (bytes 4-7), and over the wave as excl/incl (before / through this lane).
+// Headers are read with lane reads and literal lists are skipped by
+// counting terminators, so the serial walk touches LDS once per 512 bytes
+// and costs a few dozen scalar instructions per group.
+struct IndexWindow {
+    uint32_t w, total;              // wave-uniform
+    uint32_t w0, w1, c0, c1, excl, incl;  // per lane
+
+    __device__ __forceinline__ void load(IndexRing &in, uint32_t at) {
+        w = at & ~7u;
+        in.ensure(w + 528);
+        const uint32_t wb = (w >> 2) + 2 * lane();
+        w0 = in.word(wb);
+        w1 = in.word(wb + 1);
+        // One per terminator byte; times 0x01010101 gives running counts.
+        c0 = ((~w0 & 0x80808080u) >> 7) * 0x01010101u;
+        c1 = ((~w1 & 0x80808080u) >> 7) * 0x01010101u + (c0 >> 24) * 0x01010101u;
+        incl = wave_inclusive_sum32(c1 >> 24);
+        excl = incl - (c1 >> 24);
+        total = readlane(incl, kWave - 1);
+    }
+    // Byte at x (inside the window).
+    __device__ __forceinline__ uint32_t byte(uint32_t x) const {
+        const uint32_t L = (x - w) >> 3, o = (x - w) & 7;
+        const uint32_t v = o < 4 ? readlane(w0, L) : readlane(w1, L);
+        return (v >> (8 * (o & 3))) & 0xff;
+    }
+    // Terminators in [w, x) (x inside the window).
+    __device__ __forceinline__ uint32_t before(uint32_t x) const {
+        const uint32_t L = (x - w) >> 3, o = (x - w) & 7;
+        const uint64_t cc = ((uint64_t)readlane(c1, L) << 32) | readlane(c0, L);
+        return readlane(excl, L) + (o ? (uint32_t)(cc >> (8 * o - 8)) & 0xff : 0);
+    }
+    // Position of terminator number k (1-based, k <= total): in the first
+    // lane whose count through it reaches k, the first byte whose running
+    // count reaches the rest (a bytewise compare; counts are at most 8, so
+    // no borrow crosses a byte).
+    __device__ __forceinline__ uint32_t nth(uint32_t k) const {
+        const uint32_t L = (uint32_t)__builtin_ctzll(ballot(incl >= k));
+        const uint64_t r = k - readlane(excl, L);
+        const uint64_t cc = ((uint64_t)readlane(c1, L) << 32) | readlane(c0, L);
+        const uint64_t ge = ((cc | 0x8080808080808080ull) - r * 0x0101010101010101ull) & 0x8080808080808080ull;
+        return w + 8 * L + ((uint32_t)__builtin_ctzll(ge) >> 3);
+    }
+};
+
+// Index pass, one wave per chunk.  The groups it walks are cut into
+// kSplitWaves ranges of about equal output: range[c * kSplitWaves + j] =
+// (first group, end group, input position and first value of the first
+// group).  keys[2c] = the first structural error (group << 4 | -status), or
+// all ones; groups from that one on are in no range.
+__global__ void __launch_bounds__(kWave)
     rle_v1_index(const uint8_t *comp, const uint64_t *coff, uint8_t *out, const uint64_t *ooff,
-                 uint32_t n, uint2 *desc, uint32_t *count, unsigned long long *keys) {
-    __shared__ __align__(16) uint32_t s_ring[kSplitWpb][kRingLdsWords];
-    __shared__ __align__(16) uint32_t s_land[kSplitWpb][kLandWords];
-    const uint32_t wave = uni(threadIdx.x / kWave), l = lane();
-    const uint32_t c = blockIdx.x * kSplitWpb + wave;
+                 uint32_t n, uint4 *range, unsigned long long *keys) {
+    __shared__ __align__(16) uint32_t s_ring[IndexRing::kLdsWords];
+    __shared__ __align__(16) uint32_t s_land[IndexRing::kLand];
+    const uint32_t l = lane(), c = blockIdx.x;
     if (c >= n) return;
     keys[2 * c + 1] = ~0ull;  // the decode pass's key, same value from every lane
     const uint64_t i0 = coff[c], i1 = coff[c + 1], o0 = ooff[c], o1 = ooff[c + 1];
     const uint32_t in_len = (uint32_t)(i1 - i0), out_len = (uint32_t)(o1 - o0);
     if ((((i1 - i0) | (o1 - o0)) >> 31) != 0 || (out_len & 7) ||
         (reinterpret_cast<uintptr_t>(out + o0) & 7)) {
-        count[c] = 0;
+        if (l < kSplitWaves) range[(size_t)c * kSplitWaves + l] = make_uint4(0, 0, 0, 0);
         keys[2 * c] = error_key(0, CODAG_E_INVALID_ARGUMENT);
         return;
     }
-    InRing in;
-    in.init(comp + i0, in_len, s_ring[wave], s_land[wave]);
+    IndexRing in;
+    in.init(comp + i0, in_len, s_ring, s_land);
     const uint32_t end = in.gend, cap = out_len / 8;
-    uint2 *d = desc + (size_t)c * kSplitGroups;
-    uint32_t pos = in.skip, nv = 0, k = 0, dpos = 0, dn = 0;
+    uint32_t pos = in.skip, nv = 0, k = 0;
+    // Lane j < kSplitWaves: the first group of range j and where it starts.
+    uint32_t rg = 0, rpos = 0, rnv = 0, j = 0;
+    uint32_t next = 0;  // first value at which range j starts
     unsigned long long key = ~0ull;
-    bool whole = false, open_end = false;
+    bool open_end = false;
+    IndexWindow win;
+    win.load(in, pos);
     while (nv < cap) {
-        if (k == kSplitGroups) {
-            whole = true;
-            break;
-        }
         if (pos >= end) {
             key = error_key(k, CODAG_E_TRUNCATED);
             break;
         }
-        in.ensure(pos + 24);
-        uint64_t lo, hi;
-        ring_read16(in, pos, lo, hi);
-        lo = uni64(lo);
-        const int32_t h = (int8_t)(lo & 0xff);
+        if (pos + 16 > win.w + 512) win.load(in, pos);
+        const int32_t h = (int8_t)win.byte(pos);
         const uint32_t gp = pos, gn = nv;
         if (h >= 0) {
-            const uint32_t len = (uint32_t)h + 3;
-            if (pos + 2 > end) {
-                key = error_key(k, CODAG_E_TRUNCATED);
-                break;
+            // Run: header, delta byte, base varint ending at terminator e.
+            const uint32_t len = (uint32_t)h + 3, x = pos + 2;
+            const uint32_t t = win.before(x) + 1;
+            const uint32_t e = t <= win.total ? win.nth(t) : ~0u;
+            const uint32_t nb = e - x + 1;  // varint bytes (huge: none in the window)
+            if (x > end || nb >= 10 || e >= end || nv + len > cap) {
+                // The checks in decoding order; a 10-byte varint is valid
+                // when its last byte is 0 or 1.
+                const int st = x > end                                        ? CODAG_E_TRUNCATED
+                               : nb > 10 || (nb == 10 && win.byte(e) > 1) ? CODAG_E_CORRUPT
+                               : e >= end                                     ? CODAG_E_TRUNCATED
+                               : nv + len > cap                               ? CODAG_E_OVERFLOW
+                                                                              : CODAG_OK;
+                if (st != CODAG_OK) {
+                    key = error_key(k, st);
+                    break;
+                }
             }
-            hi = uni64(hi);
-            uint64_t z;
-            const uint32_t nb = varint_bytes((lo >> 16) | (hi << 48), (uint32_t)(hi >> 16), z);
-            if (nb == 0 || pos + 2 + nb > end || nv + len > cap) {
-                key = error_key(k, nb == 0               ? CODAG_E_CORRUPT
-                                   : pos + 2 + nb > end ? CODAG_E_TRUNCATED
-                                                        : CODAG_E_OVERFLOW);
-                break;
-            }
-            pos += 2 + nb;
+            pos = e + 1;
             nv += len;
         } else {
             const uint32_t len = (uint32_t)(-h);
@@ -88,61 +145,68 @@ __global__ void __launch_bounds__(kWave * kSplitWpb)
                 key = error_key(k, CODAG_E_OVERFLOW);
                 break;
             }
-            // A list that does not end inside the chunk is still recorded:
-            // its decode reports where it fails.
-            const uint32_t q = rle_skip_varints(in, pos + 1, end, len);
-            open_end = q == 0;
-            pos = q;
+            // Skip `len` varints: the list ends at terminator number t
+            // counted from the window start.  A list that does not end
+            // inside the chunk is still recorded: its decode reports where
+            // it fails.
+            uint32_t t = win.before(pos + 1) + len;
+            while (t > win.total && win.w + 512 < end) {
+                t -= win.total;
+                win.load(in, win.w + 512);
+            }
+            if (t > win.total) {
+                open_end = true;
+            } else {
+                const uint32_t e = win.nth(t);
+                open_end = e >= end;
+                pos = e + 1;
+            }
             nv += len;
         }
-        // Descriptor k goes to lane k % 64; 64 of them are stored at once.
-        dpos = l == (k & 63) ? gp : dpos;
-        dn = l == (k & 63) ? gn : dn;
-        if ((k & 63) == 63) d[(k & ~63u) + l] = make_uint2(dpos, dn);
+        // Ranges that start at or before this group's first value start here.
+        while (j < kSplitWaves && gn >= next) {
+            rg = l == j ? k : rg;
+            rpos = l == j ? gp : rpos;
+            rnv = l == j ? gn : rnv;
+            j++;
+            next = cap * j / kSplitWaves;  // cap < 2^28
+        }
         k++;
         if (open_end) break;
     }
-    if ((k & 63) != 0 && l < (k & 63)) d[(k & ~63u) + l] = make_uint2(dpos, dn);
-    if (!whole && !open_end && key == ~0ull && pos != end) key = error_key(k, CODAG_E_CORRUPT);
-    count[c] = whole ? kSplitWholeChunk : k;
-    keys[2 * c] = whole ? ~0ull : key;
+    if (!open_end && key == ~0ull && pos != end) key = error_key(k, CODAG_E_CORRUPT);
+    // Ranges not started are empty; each ends where the next one starts.
+    rg = l >= j ? k : rg;
+    const uint32_t rend = __shfl_down(rg, 1, kWave);
+    if (l < kSplitWaves) range[(size_t)c * kSplitWaves + l] = make_uint4(rg, rend, rpos, rnv);
+    keys[2 * c] = key;
     __builtin_amdgcn_s_waitcnt(0);
 }
 
-// Decode pass: wave j of chunk c decodes groups j, j + kSplitWaves, ...
+// Decode pass: wave j of chunk c decodes range j of its groups, in order,
+// streaming through the input from the range's first group.
 __global__ void __launch_bounds__(kWave * kSplitWpb)
     rle_v1_groups(const uint8_t *comp, const uint64_t *coff, uint8_t *out, const uint64_t *ooff,
-                  uint32_t n, const uint2 *desc, const uint32_t *count, unsigned long long *keys) {
-    __shared__ __align__(16) uint32_t s_ring[kSplitWpb][kRingLdsWords];
-    __shared__ __align__(16) uint32_t s_land[kSplitWpb][kLandWords];
-    __shared__ __align__(16) WaveScratch<CODAG_RLE_V1, 10, 0> s_scratch[kSplitWpb];
+                  uint32_t n, const uint4 *range, unsigned long long *keys) {
+    __shared__ __align__(16) uint32_t s_ring[kSplitWpb][GroupRing::kLdsWords];
+    __shared__ __align__(16) uint32_t s_land[kSplitWpb][GroupRing::kLand];
     const uint32_t wave = uni(threadIdx.x / kWave);
     const uint32_t gid = blockIdx.x * kSplitWpb + wave;
     const uint32_t c = gid / kSplitWaves, j = gid % kSplitWaves;
     if (c >= n) return;
-    const uint32_t cnt = uni(count[c]);
-    if (cnt == kSplitWholeChunk) {
-        if (j == 0) {
-            int st = decode_one<CODAG_RLE_V1, 10, 0>(comp, coff, out, ooff, c, s_ring[wave],
-                                                      s_land[wave], &s_scratch[wave]);
-            if (st != CODAG_OK) atomicMin(&keys[2 * c + 1], (unsigned long long)error_key(0, st));
-        }
-        return;
-    }
-    if (j >= cnt) return;
+    const uint4 r = range[(size_t)c * kSplitWaves + j];
+    const uint32_t g0 = uni(r.x), g1 = uni(r.y);
+    if (g0 >= g1) return;
     const uint64_t i0 = coff[c], i1 = coff[c + 1], o0 = ooff[c], o1 = ooff[c + 1];
-    InRing in;
-    in.init(comp + i0, (uint32_t)(i1 - i0), s_ring[wave], s_land[wave]);
+    uint32_t pos = uni(r.z), nv = uni(r.w);
+    GroupRing in;
+    in.init_at(comp + i0, (uint32_t)(i1 - i0), s_ring[wave], s_land[wave], pos);
     const uint32_t end = in.gend, cap = (uint32_t)(o1 - o0) / 8;
     uint64_t *dst = reinterpret_cast<uint64_t *>(out + o0);
-    const uint2 *d = desc + (size_t)c * kSplitGroups;
-    for (uint32_t g = j; g < cnt; g += kSplitWaves) {
-        const uint2 dd = d[g];
-        uint32_t pos = uni(dd.x), nv = uni(dd.y);
-        in.restart(pos);
+    for (uint32_t g = g0; g < g1; g++) {
         int st = rle_v1_group(in, pos, end, dst, nv, cap);
         if (st != CODAG_OK) {
-            // Later groups of this wave come later in the stream.
+            // Later groups of this range come later in the stream.
             atomicMin(&keys[2 * c + 1], (unsigned long long)error_key(g, st));
             break;
         }
@@ -166,20 +230,18 @@ int launch_rle_v1_split(const uint8_t *comp, const uint64_t *coff, uint8_t *out,
                         hipStream_t s) {
     // Workspace from the stream-ordered allocator: concurrent launches on
     // other streams get their own.
-    const size_t desc_bytes = (size_t)n * kSplitGroups * sizeof(uint2);
-    const size_t bytes = desc_bytes + (size_t)n * (sizeof(uint32_t) + 2 * sizeof(unsigned long long)) + 64;
+    const size_t range_bytes = (size_t)n * kSplitWaves * sizeof(uint4);
+    const size_t bytes = range_bytes + (size_t)n * 2 * sizeof(unsigned long long);
     void *ws = nullptr;
     if (hipMallocAsync(&ws, bytes, s) != hipSuccess) return CODAG_E_HIP;
-    uint2 *desc = static_cast<uint2 *>(ws);
+    uint4 *range = static_cast<uint4 *>(ws);
     unsigned long long *keys =
-        reinterpret_cast<unsigned long long *>(static_cast<char *>(ws) + desc_bytes);
-    uint32_t *count = reinterpret_cast<uint32_t *>(keys + 2 * (size_t)n);
-    const uint32_t ib = (n + kSplitWpb - 1) / kSplitWpb;
-    hipLaunchKernelGGL(rle_v1_index, dim3(ib), dim3(kWave * kSplitWpb), 0, s, comp, coff, out, ooff,
-                       n, desc, count, keys);
+        reinterpret_cast<unsigned long long *>(static_cast<char *>(ws) + range_bytes);
+    hipLaunchKernelGGL(rle_v1_index, dim3(n), dim3(kWave), 0, s, comp, coff, out, ooff, n, range,
+                       keys);
     const uint32_t gb = (n * kSplitWaves + kSplitWpb - 1) / kSplitWpb;
     hipLaunchKernelGGL(rle_v1_groups, dim3(gb), dim3(kWave * kSplitWpb), 0, s, comp, coff, out,
-                       ooff, n, desc, count, keys);
+                       ooff, n, range, keys);
     hipLaunchKernelGGL(rle_v1_finish, dim3((n + 255) / 256), dim3(256), 0, s, n, keys, status, err);
     hipError_t e = hipGetLastError();
     if (hipFreeAsync(ws, s) != hipSuccess || e != hipSuccess) return CODAG_E_HIP;

@@ -38,18 +38,23 @@ typedef __attribute__((address_space(3))) void lds_void;
 // the landing buffer are preceded by this explicitly.
 __device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0f70); }
 
-struct InRing {
+// F is the fetch size (a multiple of 1 KiB); the ring holds 2F bytes.
+template <uint32_t F>
+struct InRingT {
+    static constexpr uint32_t kFetch = F, kBytes = 2 * F, kWords = kBytes / 4;
+    static constexpr uint32_t kLdsWords = kWords + 4, kLand = F / 4;  // allocation sizes in words
+
     const uint8_t *gbase;  // 16-byte aligned
     uint32_t skip;         // chunk start relative to gbase (0..15)
     uint32_t gend;         // one past the chunk's last byte, relative to gbase
-    uint32_t loaded;       // bytes [loaded - kRingBytes, loaded) are in the ring
-    uint32_t *ring;        // this wave's ring (kRingLdsWords words)
-    uint32_t *land;        // this wave's landing buffer (kLandWords words)
+    uint32_t loaded;       // bytes [loaded - kBytes, loaded) are in the ring
+    uint32_t *ring;        // this wave's ring (kLdsWords words)
+    uint32_t *land;        // this wave's landing buffer (kLand words)
 
-    // Start fetching [loaded, loaded + kFetchBytes) into the landing buffer.
+    // Start fetching [loaded, loaded + kFetch) into the landing buffer.
     __device__ __forceinline__ void issue() {
 #pragma unroll
-        for (uint32_t k = 0; k < kFetchBytes / 1024; k++) {
+        for (uint32_t k = 0; k < kFetch / 1024; k++) {
             uint32_t at = loaded + 1024 * k + 16 * lane();
             if (at < gend)
                 __builtin_amdgcn_global_load_lds(gbase + at, (lds_void *)(land + 256 * k), 16, 0, 0);
@@ -69,12 +74,25 @@ struct InRing {
         issue();
     }
 
+    // As init, but decoding starts at byte position pos (relative to the
+    // chunk start rounded down to 16 bytes), so the first fetch covers it.
+    __device__ __forceinline__ void init_at(const uint8_t *chunk, uint32_t len, uint32_t *ring_lds,
+                                            uint32_t *land_lds, uint32_t pos) {
+        skip = (uint32_t)(reinterpret_cast<uintptr_t>(chunk) & 15);
+        gbase = chunk - skip;
+        gend = skip + len;
+        loaded = pos & ~(kFetch - 1);
+        ring = ring_lds;
+        land = land_lds;
+        issue();
+    }
+
     // Move the landed bytes into the ring and start fetching the next.
     __device__ __forceinline__ void commit() {
         wait_vm();
-        const uint32_t half = (loaded / kFetchBytes) & 1;
+        const uint32_t half = (loaded / kFetch) & 1;
 #pragma unroll
-        for (uint32_t k = 0; k < kFetchBytes / 1024; k++) {
+        for (uint32_t k = 0; k < kFetch / 1024; k++) {
             uint32_t at = loaded + 1024 * k + 16 * lane();
             uint4 v = reinterpret_cast<const uint4 *>(land)[64 * k + lane()];
             if (at + 16 > gend) {  // zero the bytes past the end of the chunk
@@ -88,31 +106,31 @@ struct InRing {
                 }
                 v = make_uint4(w[0], w[1], w[2], w[3]);
             }
-            reinterpret_cast<uint4 *>(ring)[half * (kFetchBytes / 16) + 64 * k + lane()] = v;
-            if (half == 0 && k == 0 && lane() == 0) reinterpret_cast<uint4 *>(ring)[kRingBytes / 16] = v;
+            reinterpret_cast<uint4 *>(ring)[half * (kFetch / 16) + 64 * k + lane()] = v;
+            if (half == 0 && k == 0 && lane() == 0) reinterpret_cast<uint4 *>(ring)[kBytes / 16] = v;
         }
-        loaded += kFetchBytes;
+        loaded += kFetch;
         issue();
     }
 
-    // Make bytes [end - kFetchBytes, end) readable.
+    // Make bytes [end - kFetch, end) readable.
     __device__ __forceinline__ void ensure(uint32_t end) {
         while (loaded < end) commit();
     }
 
     // Restart the ring at byte position pos (after a long jump ahead).
     __device__ __forceinline__ void restart(uint32_t pos) {
-        loaded = pos & ~(kFetchBytes - 1);
+        loaded = pos & ~(kFetch - 1);
         issue();
     }
 
-    __device__ __forceinline__ uint32_t word(uint32_t w) const { return ring[w & (kRingWords - 1)]; }
+    __device__ __forceinline__ uint32_t word(uint32_t w) const { return ring[w & (kWords - 1)]; }
     // Words w and w+1 (w+1 may be the mirror).
     __device__ __forceinline__ uint32_t word_next(uint32_t w) const {
-        return ring[(w & (kRingWords - 1)) + 1];
+        return ring[(w & (kWords - 1)) + 1];
     }
     __device__ __forceinline__ uint32_t word_at(uint32_t w, uint32_t k) const {
-        return ring[(w & (kRingWords - 1)) + k];
+        return ring[(w & (kWords - 1)) + k];
     }
 
     // Eight bytes starting at byte position pos, little-endian, identical on
@@ -126,10 +144,12 @@ struct InRing {
         return uni64(r);
     }
 };
+using InRing = InRingT<kFetchBytes>;
 
 // Sixteen bytes at position pos as little-endian (lo, hi) pairs, per lane
 // (needs the five words from pos >> 2 readable).
-__device__ __forceinline__ void ring_read16(const InRing &in, uint32_t pos, uint64_t &lo, uint64_t &hi) {
+template <class Ring>
+__device__ __forceinline__ void ring_read16(const Ring &in, uint32_t pos, uint64_t &lo, uint64_t &hi) {
     const uint32_t w = pos >> 2, sh = 8 * (pos & 3);
     const uint32_t a = in.word_at(w, 0), b = in.word_at(w, 1), c = in.word_at(w, 2),
                    d = in.word_at(w, 3), e = in.word_at(w, 4);
