@@ -241,10 +241,11 @@ __device__ __forceinline__ void ensure_packed_batch(InRing &in, uint32_t sec, ui
 
 // A stretch of SHORT_REPEAT runs starting at pos.  Every lane decodes the
 // 64-byte window as if a SHORT_REPEAT header started at its own byte (width,
-// count and value from the following bytes).  The wave then walks the chain
-// of runs from lane 0 with one lane read per run, marking the lanes where
-// runs start, and finally every marked lane writes its run at the position a
-// wave prefix sum of the run lengths gives it.  Stops at the first header
+// count and value from the following bytes) and links it to where the next
+// header would start.  The wave then walks the chain of runs from lane 0
+// with one lane read per run, marking the lanes where runs start, and
+// finally every marked lane writes its run at the position a wave prefix
+// sum of the run lengths gives it.  Stops at the first header
 // that is not a SHORT_REPEAT, past the window, at the end of input or when
 // the output is full, leaving pos at the next unread header.
 __device__ __forceinline__ int rle_v2_short_repeats(InRing &in, uint32_t &pos, uint32_t end,
@@ -257,35 +258,48 @@ __device__ __forceinline__ int rle_v2_short_repeats(InRing &in, uint32_t &pos, u
     const uint32_t w = ((h >> 3) & 7) + 1;
     const uint64_t vbytes = (lo >> 8) | (hi << 56);
     const uint64_t v = unzigzag(__builtin_bswap64(vbytes) >> (64 - 8 * w));
-    // Walk: integer flags keep the loop in scalar registers (values < 2^31).
-    uint32_t s = 0, m = n, bad;
+    // Each lane's run, if one starts there: where the next would start, or
+    // 0xff where the chain must stop (not a SHORT_REPEAT header, or the
+    // value past the end of the input).  The walk from lane 0 then follows
+    // these links with one lane read per run.
+    const uint32_t cs = (h & 7) + 3;
+    const uint32_t nxt = (h >> 6) == 0 && pos + l + 1 + w <= end ? l + 1 + w : 0xffu;
+    uint32_t s = 0;
     uint64_t starts = 0;
     for (;;) {
-        const uint32_t hs = readlane(h, s);
-        const uint32_t ws = ((hs >> 3) & 7) + 1, cs = (hs & 7) + 3;
-        bad = (hs >> 6) | (uint32_t)((int32_t)(cap - (m + cs)) >> 31) |
-              (uint32_t)((int32_t)(end - (pos + s + 1 + ws)) >> 31);
-        if (bad) break;
+        const uint32_t t = readlane(nxt, s);
+        if (t == 0xffu) break;
         starts |= 1ull << s;
-        m += cs;
-        s += 1 + ws;
-        // Past the window, at the end of input, or the output full.
-        if ((s >> 6) | (uint32_t)(((int32_t)(pos + s - end) >> 31) + 1) |
-            (uint32_t)(((int32_t)(m - cap) >> 31) + 1))
-            break;
+        s = t;
+        if (s >= kWave) break;
+    }
+    // Output positions of the runs in order.  A run that starts once the
+    // output is full ends the walk there; one that would pass it is an
+    // overflow; neither is stored.
+    const bool mine = (starts >> l) & 1;
+    const uint32_t c = mine ? cs : 0;
+    const uint32_t at = n + wave_inclusive_sum32(c) - c;
+    const uint64_t full = ballot(mine && at >= cap), over = ballot(mine && at < cap && at + c > cap);
+    const uint32_t ff = full ? (uint32_t)__builtin_ctzll(full) : kWave;
+    const uint32_t fo = over ? (uint32_t)__builtin_ctzll(over) : kWave;
+    const uint32_t lim = min(ff, fo);
+    if (mine && l < lim)
+        for (uint32_t j = 0; j < 10; j++)
+            if (j < c) out[at + j] = v;
+    if (fo < ff) return CODAG_E_OVERFLOW;
+    if (ff < kWave) {
+        n = cap;
+        pos += ff;
+        return CODAG_OK;
     }
     int st = CODAG_OK;
-    if (bad) {
-        const uint32_t hs = readlane(h, s), ws = ((hs >> 3) & 7) + 1, cs = (hs & 7) + 3;
-        if ((hs >> 6) == 0) st = m + cs > cap ? CODAG_E_OVERFLOW : CODAG_E_TRUNCATED;
+    n = uni(readlane(at + c, kWave - 1));
+    if (s < kWave && pos + s < end) {
+        // Stopped at a lane that is not a continuing run: a SHORT_REPEAT
+        // header there means its value is cut off by the end of input.
+        const uint32_t hs = readlane(h, s);
+        if ((hs >> 6) == 0) st = n + (hs & 7) + 3 > cap ? CODAG_E_OVERFLOW : CODAG_E_TRUNCATED;
     }
-    // The marked runs, lane-parallel.
-    const bool mine = (starts >> l) & 1;
-    const uint32_t c = mine ? (h & 7) + 3 : 0;
-    const uint32_t at = n + wave_inclusive_sum32(c) - c;
-    for (uint32_t j = 0; j < 10; j++)
-        if (j < c) out[at + j] = v;
-    n = m;
     pos += s;
     return st;
 }

@@ -172,7 +172,7 @@ def test_autotune_keeps_a_valid_fast_config(dev, small):
     best = plan.autotune(codecs, comp, co, out, oo, reps=2)
     assert best > 0
     o = plan.opts
-    assert o["waves_per_block"] in (1, 2, 4) and o["history_kib"] in (8, 16) and o["waves_per_cu"] >= 1
+    assert o["waves_per_block"] in (1, 2, 4) and o["history_kib"] in (4, 8, 16) and o["waves_per_cu"] >= 1
     (res,), _ = _run(plan, ch, dev)
     compare_chunks(*res, ref, ref_st, ch.out_offsets)
 
