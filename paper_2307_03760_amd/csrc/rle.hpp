@@ -283,9 +283,15 @@ __device__ __forceinline__ int rle_v2_short_repeats(InRing &in, uint32_t &pos, u
     const uint32_t ff = full ? (uint32_t)__builtin_ctzll(full) : kWave;
     const uint32_t fo = over ? (uint32_t)__builtin_ctzll(over) : kWave;
     const uint32_t lim = min(ff, fo);
-    if (mine && l < lim)
-        for (uint32_t j = 0; j < 10; j++)
-            if (j < c) out[at + j] = v;
+    if (mine && l < lim) {
+        // Two values per store (8-byte aligned 16-byte stores), the odd
+        // last one alone.
+        typedef uint64_t u64x2 __attribute__((ext_vector_type(2), aligned(8)));
+        const u64x2 vv = {v, v};
+        for (uint32_t j = 0; j < 10; j += 2)
+            if (j + 1 < c) *reinterpret_cast<u64x2 *>(out + at + j) = vv;
+        if (c & 1) out[at + c - 1] = v;
+    }
     if (fo < ff) return CODAG_E_OVERFLOW;
     if (ff < kWave) {
         n = cap;
