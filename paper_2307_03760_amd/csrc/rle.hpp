@@ -239,89 +239,104 @@ __device__ __forceinline__ void ensure_packed_batch(InRing &in, uint32_t sec, ui
     in.ensure(sec + (uint32_t)((last_bit + 7) >> 3) + 12);
 }
 
-// A stretch of SHORT_REPEAT runs starting at pos.  Every lane decodes the
-// 64-byte window as if a SHORT_REPEAT header started at its own byte (width,
-// count and value from the following bytes) and links it to where the next
-// header would start.  The wave then walks the chain of runs from lane 0
-// with one lane read per run, marking the lanes where runs start, and
-// finally every marked lane writes its run at the position a wave prefix
-// sum of the run lengths gives it.  Stops at the first header
-// that is not a SHORT_REPEAT, past the window, at the end of input or when
-// the output is full, leaving pos at the next unread header.
+// A stretch of SHORT_REPEAT runs starting at pos, 64 bytes at a time.
+// Every lane decodes the window as if a SHORT_REPEAT header started at its
+// own byte (width, count and value from the following bytes) and links it
+// to where the next header would start.  The wave then walks the chain of
+// runs from lane 0 with one lane read per run, marking the lanes where runs
+// start, and every marked lane writes its run at the position a wave prefix
+// sum of the run lengths gives it; a chain that runs past the window goes
+// on in the next one.  Stops at the first header that is not a
+// SHORT_REPEAT, at the end of input or when the output is full, leaving pos
+// at the next unread header; when that header lies in the window, its first
+// eight bytes are returned in x (next = true).
 __device__ __forceinline__ int rle_v2_short_repeats(InRing &in, uint32_t &pos, uint32_t end,
-                                                    uint64_t *out, uint32_t &n, uint32_t cap) {
+                                                    uint64_t *out, uint32_t &n, uint32_t cap,
+                                                    uint64_t &x, bool &next) {
     const uint32_t l = lane();
-    in.ensure(pos + 84);
-    uint64_t lo, hi;
-    ring_read16(in, pos + l, lo, hi);
-    const uint32_t h = (uint32_t)(lo & 0xff);
-    const uint32_t w = ((h >> 3) & 7) + 1;
-    const uint64_t vbytes = (lo >> 8) | (hi << 56);
-    const uint64_t v = unzigzag(__builtin_bswap64(vbytes) >> (64 - 8 * w));
-    // Each lane's run, if one starts there: where the next would start, or
-    // 0xff where the chain must stop (not a SHORT_REPEAT header, or the
-    // value past the end of the input).  The walk from lane 0 then follows
-    // these links with one lane read per run.
-    const uint32_t cs = (h & 7) + 3;
-    const uint32_t nxt = (h >> 6) == 0 && pos + l + 1 + w <= end ? l + 1 + w : 0xffu;
-    uint32_t s = 0;
-    uint64_t starts = 0;
     for (;;) {
-        const uint32_t t = readlane(nxt, s);
-        if (t == 0xffu) break;
-        starts |= 1ull << s;
-        s = t;
-        if (s >= kWave) break;
+        in.ensure(pos + 84);
+        uint64_t lo, hi;
+        ring_read16(in, pos + l, lo, hi);
+        const uint32_t h = (uint32_t)(lo & 0xff);
+        const uint32_t w = ((h >> 3) & 7) + 1;
+        const uint64_t vbytes = (lo >> 8) | (hi << 56);
+        const uint64_t v = unzigzag(__builtin_bswap64(vbytes) >> (64 - 8 * w));
+        // Each lane's run, if one starts there: where the next would start,
+        // or 0xff where the chain must stop (not a SHORT_REPEAT header, or
+        // the value past the end of the input).
+        const uint32_t cs = (h & 7) + 3;
+        const uint32_t nxt = (h >> 6) == 0 && pos + l + 1 + w <= end ? l + 1 + w : 0xffu;
+        uint32_t s = 0;
+        uint64_t starts = 0;
+        for (;;) {
+            const uint32_t t = readlane(nxt, s);
+            if (t == 0xffu) break;
+            starts |= 1ull << s;
+            s = t;
+            if (s >= kWave) break;
+        }
+        // Output positions of the runs in order.  A run that starts once
+        // the output is full ends the walk there; one that would pass it is
+        // an overflow; neither is stored.
+        const bool mine = (starts >> l) & 1;
+        const uint32_t c = mine ? cs : 0;
+        const uint32_t at = n + wave_inclusive_sum32(c) - c;
+        const uint64_t full = ballot(mine && at >= cap), over = ballot(mine && at < cap && at + c > cap);
+        const uint32_t ff = full ? (uint32_t)__builtin_ctzll(full) : kWave;
+        const uint32_t fo = over ? (uint32_t)__builtin_ctzll(over) : kWave;
+        const uint32_t lim = min(ff, fo);
+        if (mine && l < lim) {
+            // Two values per store (8-byte aligned 16-byte stores), the odd
+            // last one alone.
+            typedef uint64_t u64x2 __attribute__((ext_vector_type(2), aligned(8)));
+            const u64x2 vv = {v, v};
+            for (uint32_t j = 0; j < 10; j += 2)
+                if (j + 1 < c) *reinterpret_cast<u64x2 *>(out + at + j) = vv;
+            if (c & 1) out[at + c - 1] = v;
+        }
+        if (fo < ff) return CODAG_E_OVERFLOW;
+        if (ff < kWave) {
+            n = cap;
+            pos += ff;
+            return CODAG_OK;
+        }
+        n = uni(readlane(at + c, kWave - 1));
+        if (s < kWave) {
+            // Stopped at a lane that does not continue the chain: a
+            // SHORT_REPEAT header inside the input there has its value cut
+            // off; any other header is handed back.
+            int st = CODAG_OK;
+            if (pos + s < end) {
+                const uint32_t hs = readlane(h, s);
+                if ((hs >> 6) == 0)
+                    st = n + (hs & 7) + 3 > cap ? CODAG_E_OVERFLOW : CODAG_E_TRUNCATED;
+                x = uni64(readlane64(lo, s));
+                next = true;
+            }
+            pos += s;
+            return st;
+        }
+        pos += s;
+        if (n >= cap || pos >= end) return CODAG_OK;
     }
-    // Output positions of the runs in order.  A run that starts once the
-    // output is full ends the walk there; one that would pass it is an
-    // overflow; neither is stored.
-    const bool mine = (starts >> l) & 1;
-    const uint32_t c = mine ? cs : 0;
-    const uint32_t at = n + wave_inclusive_sum32(c) - c;
-    const uint64_t full = ballot(mine && at >= cap), over = ballot(mine && at < cap && at + c > cap);
-    const uint32_t ff = full ? (uint32_t)__builtin_ctzll(full) : kWave;
-    const uint32_t fo = over ? (uint32_t)__builtin_ctzll(over) : kWave;
-    const uint32_t lim = min(ff, fo);
-    if (mine && l < lim) {
-        // Two values per store (8-byte aligned 16-byte stores), the odd
-        // last one alone.
-        typedef uint64_t u64x2 __attribute__((ext_vector_type(2), aligned(8)));
-        const u64x2 vv = {v, v};
-        for (uint32_t j = 0; j < 10; j += 2)
-            if (j + 1 < c) *reinterpret_cast<u64x2 *>(out + at + j) = vv;
-        if (c & 1) out[at + c - 1] = v;
-    }
-    if (fo < ff) return CODAG_E_OVERFLOW;
-    if (ff < kWave) {
-        n = cap;
-        pos += ff;
-        return CODAG_OK;
-    }
-    int st = CODAG_OK;
-    n = uni(readlane(at + c, kWave - 1));
-    if (s < kWave && pos + s < end) {
-        // Stopped at a lane that is not a continuing run: a SHORT_REPEAT
-        // header there means its value is cut off by the end of input.
-        const uint32_t hs = readlane(h, s);
-        if ((hs >> 6) == 0) st = n + (hs & 7) + 3 > cap ? CODAG_E_OVERFLOW : CODAG_E_TRUNCATED;
-    }
-    pos += s;
-    return st;
 }
 
 __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t cap) {
     uint32_t pos = in.skip, end = in.gend;
     uint32_t n = 0;
     const uint32_t l = lane();
+    uint64_t x = 0;     // the header's first eight bytes
+    bool have = false;  // x already read (handed back by a SHORT_REPEAT stretch)
     while (n < cap) {
         if (pos >= end) return CODAG_E_TRUNCATED;
         in.ensure(pos + 24);
-        uint64_t x = in.peek8(pos);
+        if (!have) x = in.peek8(pos);
+        have = false;
         uint32_t b0 = (uint32_t)(x & 0xff), type = b0 >> 6;
         if (type == 0) {
             // SHORT_REPEAT: byte width and count in the header, then the value.
-            int st = rle_v2_short_repeats(in, pos, end, out, n, cap);
+            int st = rle_v2_short_repeats(in, pos, end, out, n, cap, x, have);
             if (st) return st;
             continue;
         }
