@@ -414,18 +414,20 @@ __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t
             bool filler = gap == 255 && patch == 0;
             uint64_t cursor = wave_inclusive_sum(gap);
             if (ballot(l < pll && !filler && cursor >= len)) return CODAG_E_CORRUPT;
+            // Patch j lands on value cursor[j] (below 2^13: at most 31
+            // gaps below 2^8).  A filler entry's patch is zero, so OR-ing it
+            // in changes nothing and needs no test.
+            const uint32_t cur = (uint32_t)cursor, plo = (uint32_t)patch, phi = (uint32_t)(patch >> 32);
             uint32_t jp = 0;
             for (uint32_t i0 = 0; i0 < len; i0 += kWave) {
                 if (!whole) ensure_packed_batch(in, dsec, i0, w);
                 uint32_t i = i0 + l;
                 uint64_t v = i < len ? packed_value(in, dsec, i, w) : 0;
                 while (jp < pll) {
-                    uint32_t pj = (uint32_t)readlane64(cursor, jp);
+                    const uint32_t pj = readlane(cur, jp);
                     if (pj >= i0 + kWave) break;
-                    if (!(readlane64(gap, jp) == 255 && readlane64(patch, jp) == 0)) {
-                        uint64_t pt = readlane64(patch, jp);
-                        if (i == pj) v |= pt << w;
-                    }
+                    const uint64_t pt = ((uint64_t)readlane(phi, jp) << 32) | readlane(plo, jp);
+                    if (i == pj) v |= pt << w;
                     jp++;
                 }
                 if (i < len) out[n + i] = base + v;
