@@ -230,6 +230,14 @@ __device__ __forceinline__ uint64_t packed_value(const InRing &in, uint32_t sec,
     return ring_bits_msb(in, 8ull * sec + (uint64_t)i * w, w);
 }
 
+// The same for widths of at most 32 bits: two ring words always hold the
+// value (its first bit is at most 31 bits into the first word).
+__device__ __forceinline__ uint32_t packed_value32(const InRing &in, uint32_t sec, uint32_t i, uint32_t w) {
+    const uint32_t bit = 8 * sec + i * w, wi = bit >> 5;
+    const uint64_t x = ((uint64_t)bswap32(in.word_at(wi, 0)) << 32) | bswap32(in.word_at(wi, 1));
+    return (uint32_t)((x << (bit & 31)) >> (64 - w));
+}
+
 // A packed section this long (plus a few bytes of lookahead) is readable in
 // the ring at once.
 constexpr uint32_t kWholeSection = kFetchBytes - 32;
@@ -353,10 +361,18 @@ __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t
                 // The whole section is readable at once: eight unrolled
                 // batches, so their LDS reads overlap.
                 in.ensure(sec + nbytes + 12);
+                if (w <= 32) {
 #pragma unroll
-                for (uint32_t b = 0; b < 8; b++) {
-                    uint32_t i = kWave * b + l;
-                    if (i < len) out[n + i] = unzigzag(packed_value(in, sec, i, w));
+                    for (uint32_t b = 0; b < 8; b++) {
+                        uint32_t i = kWave * b + l;
+                        if (i < len) out[n + i] = unzigzag(packed_value32(in, sec, i, w));
+                    }
+                } else {
+#pragma unroll
+                    for (uint32_t b = 0; b < 8; b++) {
+                        uint32_t i = kWave * b + l;
+                        if (i < len) out[n + i] = unzigzag(packed_value(in, sec, i, w));
+                    }
                 }
             } else {
                 for (uint32_t i0 = 0; i0 < len; i0 += kWave) {
@@ -422,7 +438,7 @@ __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t
             for (uint32_t i0 = 0; i0 < len; i0 += kWave) {
                 if (!whole) ensure_packed_batch(in, dsec, i0, w);
                 uint32_t i = i0 + l;
-                uint64_t v = i < len ? packed_value(in, dsec, i, w) : 0;
+                uint64_t v = i >= len ? 0 : w <= 32 ? packed_value32(in, dsec, i, w) : packed_value(in, dsec, i, w);
                 while (jp < pll) {
                     const uint32_t pj = readlane(cur, jp);
                     if (pj >= i0 + kWave) break;
@@ -484,14 +500,30 @@ __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t
                 uint64_t prev = base + dbase;
                 const bool whole = nbytes <= kWholeSection;
                 if (whole) in.ensure(p + nbytes + 12);
-                for (uint32_t i0 = 0; i0 < nd; i0 += kWave) {
-                    if (!whole) ensure_packed_batch(in, p, i0, w);
-                    uint32_t i = i0 + l;
-                    uint64_t d = i < nd ? packed_value(in, p, i, w) : 0;
-                    uint64_t s = wave_inclusive_sum(d);
-                    uint64_t v = neg ? prev - s : prev + s;
-                    if (i < nd) out[n + 2 + i] = v;
-                    prev = uni64(readlane64(v, kWave - 1));
+                if (whole && w <= 24) {
+                    // Narrow deltas: a batch's sums fit 32 bits (64 x 2^24),
+                    // and the batches only share the running value, so
+                    // their reads and scans overlap.
+#pragma unroll
+                    for (uint32_t b = 0; b < 8; b++) {
+                        const uint32_t i = kWave * b + l;
+                        const uint32_t d = i < nd ? packed_value32(in, p, i, w) : 0;
+                        const uint32_t s = wave_inclusive_sum32(d);
+                        const uint64_t v = neg ? prev - s : prev + s;
+                        if (i < nd) out[n + 2 + i] = v;
+                        const uint32_t t = uni(readlane(s, kWave - 1));
+                        prev = neg ? prev - t : prev + t;
+                    }
+                } else {
+                    for (uint32_t i0 = 0; i0 < nd; i0 += kWave) {
+                        if (!whole) ensure_packed_batch(in, p, i0, w);
+                        uint32_t i = i0 + l;
+                        uint64_t d = i < nd ? packed_value(in, p, i, w) : 0;
+                        uint64_t s = wave_inclusive_sum(d);
+                        uint64_t v = neg ? prev - s : prev + s;
+                        if (i < nd) out[n + 2 + i] = v;
+                        prev = uni64(readlane64(v, kWave - 1));
+                    }
                 }
                 pos = p + nbytes;
             }
