@@ -109,7 +109,7 @@ def test_rle_extremes(dev):
             (np.uint64(I64_MAX - 200) + np.arange(500, dtype=np.uint64)).view(np.int64),
             np.random.default_rng(3).integers(I64_MIN, I64_MAX, 777, dtype=np.int64),
             # 4,000 groups in one chunk (a run of three and a one-value list, repeated):
-            # more groups than the group-parallel index keeps per chunk.
+            # the group-parallel ranges hold hundreds of short groups each.
             np.column_stack([np.repeat(np.random.default_rng(4).integers(-9999, 9999, 2000), 3).reshape(-1, 3),
                              np.random.default_rng(5).integers(I64_MIN, I64_MAX, 2000)]).reshape(-1)]
     for codec, encode, gp in ((oracle.RLE_V1, enc.encode_rle_v1, 1), (oracle.RLE_V1, enc.encode_rle_v1, 2),
