@@ -270,19 +270,22 @@ __device__ __forceinline__ int rle_v2_short_repeats(InRing &in, uint32_t &pos, u
         const uint32_t w = ((h >> 3) & 7) + 1;
         const uint64_t vbytes = (lo >> 8) | (hi << 56);
         const uint64_t v = unzigzag(__builtin_bswap64(vbytes) >> (64 - 8 * w));
-        // Each lane's run, if one starts there: where the next would start,
-        // or 0xff where the chain must stop (not a SHORT_REPEAT header, or
-        // the value past the end of the input).
+        // Each lane's run, if one starts there: where the next would start
+        // (below 128), or 128 + lane where the chain must stop (not a
+        // SHORT_REPEAT header, or the value past the end of the input).  The
+        // walk's only dependent step is the lane read; a stop lane it marked
+        // is unmarked afterwards.
         const uint32_t cs = (h & 7) + 3;
-        const uint32_t nxt = (h >> 6) == 0 && pos + l + 1 + w <= end ? l + 1 + w : 0xffu;
+        const uint32_t nxt = (h >> 6) == 0 && pos + l + 1 + w <= end ? l + 1 + w : 128 + l;
         uint32_t s = 0;
         uint64_t starts = 0;
-        for (;;) {
-            const uint32_t t = readlane(nxt, s);
-            if (t == 0xffu) break;
+        do {
             starts |= 1ull << s;
-            s = t;
-            if (s >= kWave) break;
+            s = readlane(nxt, s);
+        } while (s < kWave);
+        if (s >= 128) {
+            s -= 128;
+            starts &= ~(1ull << s);
         }
         // Output positions of the runs in order.  A run that starts once
         // the output is full ends the walk there; one that would pass it is
