@@ -377,6 +377,26 @@ __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t
                         if (i < len) out[n + i] = unzigzag(packed_value(in, sec, i, w));
                     }
                 }
+            } else if (w <= 32) {
+                // Two batches per ring check (at most 512 bytes together).
+                for (uint32_t i0 = 0; i0 < len; i0 += 2 * kWave) {
+                    ensure_packed_batch(in, sec, i0 + kWave, w);
+                    const uint32_t i = i0 + l, j = i + kWave;
+                    const uint32_t a = i < len ? packed_value32(in, sec, i, w) : 0;
+                    const uint32_t b = j < len ? packed_value32(in, sec, j, w) : 0;
+                    if (i < len) out[n + i] = unzigzag(a);
+                    if (j < len) out[n + j] = unzigzag(b);
+                }
+            } else if (w <= 56) {
+                // Two batches per ring check (at most 896 bytes together).
+                for (uint32_t i0 = 0; i0 < len; i0 += 2 * kWave) {
+                    ensure_packed_batch(in, sec, i0 + kWave, w);
+                    const uint32_t i = i0 + l, j = i + kWave;
+                    const uint64_t a = i < len ? packed_value(in, sec, i, w) : 0;
+                    const uint64_t b = j < len ? packed_value(in, sec, j, w) : 0;
+                    if (i < len) out[n + i] = unzigzag(a);
+                    if (j < len) out[n + j] = unzigzag(b);
+                }
             } else {
                 for (uint32_t i0 = 0; i0 < len; i0 += kWave) {
                     ensure_packed_batch(in, sec, i0, w);
@@ -438,6 +458,33 @@ __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t
             // in changes nothing and needs no test.
             const uint32_t cur = (uint32_t)cursor, plo = (uint32_t)patch, phi = (uint32_t)(patch >> 32);
             uint32_t jp = 0;
+            if (whole && w <= 32) {
+                // All eight batches' values first, so their LDS reads
+                // overlap; then the patches and the stores.
+                uint32_t vb[8];
+#pragma unroll
+                for (uint32_t b = 0; b < 8; b++) {
+                    const uint32_t i = kWave * b + l;
+                    vb[b] = i < len ? packed_value32(in, dsec, i, w) : 0;
+                }
+#pragma unroll
+                for (uint32_t b = 0; b < 8; b++) {
+                    const uint32_t i0 = kWave * b, i = i0 + l;
+                    if (i0 >= len) break;
+                    uint64_t v = vb[b];
+                    while (jp < pll) {
+                        const uint32_t pj = readlane(cur, jp);
+                        if (pj >= i0 + kWave) break;
+                        const uint64_t pt = ((uint64_t)readlane(phi, jp) << 32) | readlane(plo, jp);
+                        if (i == pj) v |= pt << w;
+                        jp++;
+                    }
+                    if (i < len) out[n + i] = base + v;
+                }
+                pos = psec + pbytes;
+                n += len;
+                continue;
+            }
             for (uint32_t i0 = 0; i0 < len; i0 += kWave) {
                 if (!whole) ensure_packed_batch(in, dsec, i0, w);
                 uint32_t i = i0 + l;
