@@ -613,28 +613,30 @@ __device__ __forceinline__ int inflate_batched(InRing &in, BitIn &bi, WindowOut<
             // bounds are checked lane-parallel once the batch is complete.
             // Exits: a token the batch cannot take, the end of the window,
             // a full batch (flags by integer arithmetic: values < 2^31).
-            uint32_t t = 0, inf;
-            for (;;) {
-                inf = readlane(info, t);
-                if (inf & kTokStop) break;
-                const uint32_t d = readlane(dist, t);
-                tok = l == ntok ? inf : tok;
-                tdist = l == ntok ? d : tdist;
-                tpos = l == ntok ? p + t : tpos;
-                t += (inf >> 8) & 63;
-                ntok++;
-                bout += inf >> 16;
-                if ((t >> 6) | (ntok >> 6) | (uint32_t)((int32_t)(kBatchOut - 258 - bout) >> 31)) break;
-            }
-            if (inf & kTokStop) {
-                if (inf == (kTokStop | (inf & 0x3f00))) {  // end of block
+            // One exit test per token: the next token is read before the
+            // test (a harmless read when the window or batch is done).
+            uint32_t t = 0, full = 0, inf = readlane(info, 0);
+            if (!(inf & kTokStop)) {
+                for (;;) {
+                    const uint32_t d = readlane(dist, t);
+                    tok = l == ntok ? inf : tok;
+                    tdist = l == ntok ? d : tdist;
+                    tpos = l == ntok ? p + t : tpos;
                     t += (inf >> 8) & 63;
-                    stop = 2;
-                } else {
-                    stop = 3;
+                    ntok++;
+                    bout += inf >> 16;
+                    full = ((t | ntok) >> 6) | (uint32_t)((int32_t)(kBatchOut - 258 - bout) >> 31);
+                    inf = readlane(info, t & 63);
+                    if (full | (inf & kTokStop)) break;
                 }
-            } else if (ntok == kWave || bout > kBatchOut - 258) {
-                stop = 1;  // batch full
+            }
+            if (full) {
+                if (ntok == kWave || bout > kBatchOut - 258) stop = 1;  // batch full
+            } else if (inf == (kTokStop | (inf & 0x3f00))) {      // end of block
+                t += (inf >> 8) & 63;
+                stop = 2;
+            } else {
+                stop = 3;
             }
             p += t;
         } while (stop == 0);
