@@ -1,10 +1,12 @@
 // input_stream for one wavefront (CODAG Section IV-B, IV-E).
 //
-// The chunk's compressed bytes reach the wave through a 2 KiB ring in LDS,
-// refilled 1 KiB at a time (the "conditional A" refill of Section IV-A).
-// Each kilobyte is fetched by one 16-byte direct-to-LDS load per lane into a
-// separate landing buffer while the previous kilobyte is being decoded, and
-// moved into the ring when decoding crosses into it.  Keeping the in-flight
+// The chunk's compressed bytes reach the wave through a ring in LDS of twice
+// the fetch size, refilled one fetch at a time (the "conditional A" refill
+// of Section IV-A); the decoders use 1 KiB fetches, the group-parallel RLE
+// v1 passes 4 and 8 KiB.  Each kilobyte is fetched by one 16-byte
+// direct-to-LDS load per lane into a separate landing buffer while the
+// previous fetch is being decoded, and moved into the ring when decoding
+// crosses into it.  Keeping the in-flight
 // data out of vector registers matters on this architecture: one counter
 // tracks both loads and stores, so waiting on an in-flight register load
 // would also wait for every output store issued since.  The landing buffer
