@@ -35,7 +35,7 @@ using GroupRing = InRingT<4096>;
 // (bytes 4-7), and over the wave as excl/incl (before / through this lane).
 // Headers are read with lane reads and literal lists are skipped by
 // counting terminators, so the serial walk touches LDS once per 512 bytes
-// and costs a few dozen scalar instructions per group.
+// and each group is one chain of lane reads and scalar instructions.
 struct IndexWindow {
     uint32_t w, total;              // wave-uniform
     uint32_t w0, w1, c0, c1, excl, incl;  // per lane
