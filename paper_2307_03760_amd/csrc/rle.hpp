@@ -293,9 +293,13 @@ __device__ __forceinline__ int rle_v2_short_repeats(InRing &in, uint32_t &pos, u
         const bool mine = (starts >> l) & 1;
         const uint32_t c = mine ? cs : 0;
         const uint32_t at = n + wave_inclusive_sum32(c) - c;
-        const uint64_t full = ballot(mine && at >= cap), over = ballot(mine && at < cap && at + c > cap);
-        const uint32_t ff = full ? (uint32_t)__builtin_ctzll(full) : kWave;
-        const uint32_t fo = over ? (uint32_t)__builtin_ctzll(over) : kWave;
+        const uint32_t n1 = uni(readlane(at + c, kWave - 1));
+        uint32_t ff = kWave, fo = kWave;
+        if (n1 > cap) {  // the output fills inside this window
+            const uint64_t full = ballot(mine && at >= cap), over = ballot(mine && at < cap && at + c > cap);
+            ff = full ? (uint32_t)__builtin_ctzll(full) : kWave;
+            fo = over ? (uint32_t)__builtin_ctzll(over) : kWave;
+        }
         const uint32_t lim = min(ff, fo);
         if (mine && l < lim) {
             // Two values per store (8-byte aligned 16-byte stores), the odd
@@ -312,7 +316,7 @@ __device__ __forceinline__ int rle_v2_short_repeats(InRing &in, uint32_t &pos, u
             pos += ff;
             return CODAG_OK;
         }
-        n = uni(readlane(at + c, kWave - 1));
+        n = n1;
         if (s < kWave) {
             // Stopped at a lane that does not continue the chain: a
             // SHORT_REPEAT header inside the input there has its value cut
@@ -418,7 +422,9 @@ __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t
             if (n + len > cap) return CODAG_E_OVERFLOW;
             uint32_t bsec = pos + 4;
             if (bsec + bw > end) return CODAG_E_TRUNCATED;
-            uint64_t braw = bytes_be(in.peek8(bsec), bw);
+            // The base's bytes follow the 4-byte header: up to four of them
+            // are already in x.
+            uint64_t braw = bytes_be(bw <= 4 ? x >> 32 : in.peek8(bsec), bw);
             uint64_t sign = 1ull << (8 * bw - 1);
             uint64_t base = (braw & sign) ? 0 - (braw & ~sign) : braw;
             uint32_t dsec = bsec + bw, dbytes = (len * w + 7) >> 3;
