@@ -37,6 +37,7 @@
 #include "oracle.h"
 
 #include <stddef.h>
+#include <stdlib.h>
 #include <string.h>
 
 /* ------------------------------------------------------------------ */
@@ -368,60 +369,74 @@ static int bits(bit_reader *r, int n, uint32_t *v) {
     return ORACLE_OK;
 }
 
-/* Canonical Huffman code (RFC 1951 section 3.2.2): codes of equal length
- * are consecutive and ordered by symbol; shorter codes precede longer. */
+/* Huffman codes as RFC 1951 section 3.2.2 defines them from the code length
+ * of every symbol: codes of one length are consecutive integers taken in
+ * increasing symbol order, and the first code of a length is the code after
+ * the last one of the previous length, doubled.  A code is read from the
+ * stream most significant bit first, so after L bits the bits read form an
+ * L-bit integer; the pair (L, that integer) is looked up in a table keyed by
+ * 2^L + integer, a key that differs for every pair (L <= 15, so keys are
+ * below 2^16).  A code's table is reused by the blocks of a decode; only the
+ * keys the previous code set are cleared again. */
+#define HUFF_KEYS (1 << 16)
 typedef struct {
-    int count[16];   /* number of codes of each length */
-    int symbol[320]; /* symbols ordered by (length, symbol) */
+    int16_t *symbol_of;   /* HUFF_KEYS entries: symbol for key 2^L + code, or -1 */
+    uint32_t keys[320];   /* the keys this code set */
+    int nkeys;
+    long kraft;           /* sum over coded symbols of 2^(15 - L) */
+    int ones;             /* codes of length 1 */
 } huffman;
 
-/* Returns 0 for a complete code, > 0 for an incomplete one (the number of
- * unused codes of length 15), < 0 if over-subscribed. */
-static int huff_build(huffman *h, const int *lengths, int n) {
-    int offs[16], len, sym, left;
-    for (len = 0; len < 16; len++) h->count[len] = 0;
-    for (sym = 0; sym < n; sym++) h->count[lengths[sym]]++;
-    left = 1;
+/* Assigns codes to lengths[0..n) (RFC 1951 section 3.2.2, steps 1 to 3).
+ * Over-subscribed sets (Kraft sum above 1) get no codes. */
+static void huff_build(huffman *h, const int *lengths, int n) {
+    int length_count[16], next_code[16], len, sym, code;
+    while (h->nkeys > 0) h->symbol_of[h->keys[--h->nkeys]] = -1;
+    for (len = 0; len < 16; len++) length_count[len] = 0;
+    for (sym = 0; sym < n; sym++) length_count[lengths[sym]]++;
+    h->kraft = 0;
+    for (len = 1; len < 16; len++) h->kraft += (long)length_count[len] << (15 - len);
+    h->ones = length_count[1];
+    if (h->kraft > (1L << 15)) return;
+    code = 0;
+    length_count[0] = 0;
     for (len = 1; len < 16; len++) {
-        left <<= 1;
-        left -= h->count[len];
-        if (left < 0) return left;
+        code = (code + length_count[len - 1]) << 1;
+        next_code[len] = code;
     }
-    offs[1] = 0;
-    for (len = 1; len < 15; len++) offs[len + 1] = offs[len] + h->count[len];
-    for (sym = 0; sym < n; sym++)
-        if (lengths[sym] != 0) h->symbol[offs[lengths[sym]]++] = sym;
-    return left;
+    for (sym = 0; sym < n; sym++) {
+        len = lengths[sym];
+        if (len != 0) {
+            uint32_t key = (1u << len) | (uint32_t)next_code[len]++;
+            h->symbol_of[key] = (int16_t)sym;
+            h->keys[h->nkeys++] = key;
+        }
+    }
 }
 
-/* Whether a set of lengths is usable: complete, or the one allowed
- * incomplete form of exactly one code of length 1 (RFC 1951 section 3.2.7
- * permits a single code), or (for distances only) no codes at all. */
-static int huff_usable(const huffman *h, int left, int allow_empty) {
-    int len, total = 0;
-    if (left < 0) return 0;
-    for (len = 1; len < 16; len++) total += h->count[len];
-    if (total == 0) return allow_empty;
-    if (left == 0) return 1;
-    return total == 1 && h->count[1] == 1;
+/* Whether the code can be used (RFC 1951 section 3.2.7 and the readings
+ * above): not over-subscribed, and complete, except that a single code of
+ * length 1 is allowed and, where allow_empty, no codes at all. */
+static int huff_usable(const huffman *h, int allow_empty) {
+    if (h->kraft > (1L << 15)) return 0;
+    if (h->nkeys == 0) return allow_empty;
+    if (h->kraft == (1L << 15)) return 1;
+    return h->nkeys == 1 && h->ones == 1;
 }
 
-/* Decode one symbol, reading code bits most significant first. */
+/* Decode one symbol: take code bits one at a time, most significant first,
+ * until the bits read so far are a code. */
 static int huff_decode(bit_reader *r, const huffman *h, int *sym) {
-    int code = 0, first = 0, index = 0, len;
+    uint32_t key = 1;
+    int len;
     for (len = 1; len < 16; len++) {
-        int count = h->count[len];
-        code |= bit_at(r, r->bitpos + len - 1);
-        if (code - count < first) {
+        key = (key << 1) | (uint32_t)bit_at(r, r->bitpos + len - 1);
+        if (h->symbol_of[key] >= 0) {
             if (r->bitpos + (uint64_t)len > r->nbits) return ORACLE_E_TRUNCATED;
             r->bitpos += len;
-            *sym = h->symbol[index + (code - first)];
+            *sym = h->symbol_of[key];
             return ORACLE_OK;
         }
-        index += count;
-        first += count;
-        first <<= 1;
-        code <<= 1;
     }
     return ORACLE_E_CORRUPT; /* matches no code */
 }
@@ -448,8 +463,12 @@ typedef struct {
     uint64_t n;
 } out_window;
 
-static int inflate_codes(bit_reader *r, out_window *o, const huffman *lit,
-                         const huffman *dist, int have_dist) {
+/* The literal/length and distance codes of one block (RFC 1951 section
+ * 3.2.5): literals are copied out, 256 ends the block, 257..285 start a
+ * <length, backward distance> pair whose bytes are copied from the output
+ * already produced. */
+static int inflate_block_codes(bit_reader *r, out_window *o, const huffman *lit,
+                               const huffman *dist) {
     for (;;) {
         int sym, st;
         st = huff_decode(r, lit, &sym);
@@ -462,35 +481,37 @@ static int inflate_codes(bit_reader *r, out_window *o, const huffman *lit,
         } else {
             int lbase, lextra, dsym, dbase, dextra;
             uint32_t x;
-            uint64_t len, d, k;
+            uint64_t length, distance, k;
             if (sym > 285) return ORACLE_E_CORRUPT;
             length_code(sym, &lbase, &lextra);
             st = bits(r, lextra, &x);
             if (st) return st;
-            len = (uint64_t)lbase + x;
-            if (!have_dist) return ORACLE_E_CORRUPT;
+            length = (uint64_t)lbase + x;
+            if (dist->nkeys == 0) return ORACLE_E_CORRUPT; /* no distance codes */
             st = huff_decode(r, dist, &dsym);
             if (st) return st;
             if (dsym > 29) return ORACLE_E_CORRUPT;
             distance_code(dsym, &dbase, &dextra);
             st = bits(r, dextra, &x);
             if (st) return st;
-            d = (uint64_t)dbase + x;
-            if (d > o->n) return ORACLE_E_CORRUPT;     /* before the chunk */
-            if (o->n + len > o->cap) return ORACLE_E_OVERFLOW;
-            for (k = 0; k < len; k++) { /* byte by byte: overlap repeats */
-                o->out[o->n] = o->out[o->n - d];
+            distance = (uint64_t)dbase + x;
+            if (distance > o->n) return ORACLE_E_CORRUPT;     /* before the chunk */
+            if (o->n + length > o->cap) return ORACLE_E_OVERFLOW;
+            for (k = 0; k < length; k++) { /* byte by byte: overlap repeats */
+                o->out[o->n] = o->out[o->n - distance];
                 o->n++;
             }
         }
     }
 }
 
+/* A stored block (RFC 1951 section 3.2.4): skip to a byte boundary, LEN and
+ * its one's complement NLEN, then LEN literal bytes. */
 static int inflate_stored(bit_reader *r, out_window *o) {
     uint32_t len, nlen;
     uint64_t k;
     int st;
-    r->bitpos = (r->bitpos + 7) & ~(uint64_t)7; /* to a byte boundary */
+    r->bitpos = (r->bitpos + 7) & ~(uint64_t)7;
     st = bits(r, 16, &len);
     if (st) return st;
     st = bits(r, 16, &nlen);
@@ -503,88 +524,95 @@ static int inflate_stored(bit_reader *r, out_window *o) {
     return ORACLE_OK;
 }
 
-static int inflate_fixed(bit_reader *r, out_window *o) {
-    int lengths[320], sym;
-    huffman lit, dist;
-    for (sym = 0; sym < 144; sym++) lengths[sym] = 8;
-    for (; sym < 256; sym++) lengths[sym] = 9;
-    for (; sym < 280; sym++) lengths[sym] = 7;
-    for (; sym < 288; sym++) lengths[sym] = 8;
-    huff_build(&lit, lengths, 288);
-    for (sym = 0; sym < 32; sym++) lengths[sym] = 5;
-    huff_build(&dist, lengths, 32);
-    return inflate_codes(r, o, &lit, &dist, 1);
+/* The three codes a decode needs, each with its own key table. */
+typedef struct {
+    huffman lit, dist, clen;
+} code_set;
+
+/* A block with the fixed codes of RFC 1951 section 3.2.6. */
+static int inflate_fixed(bit_reader *r, out_window *o, code_set *c) {
+    int lengths[288], sym;
+    for (sym = 0; sym < 288; sym++)
+        lengths[sym] = sym < 144 ? 8 : sym < 256 ? 9 : sym < 280 ? 7 : 8;
+    huff_build(&c->lit, lengths, 288);
+    for (sym = 0; sym < 30; sym++) lengths[sym] = 5;
+    lengths[30] = lengths[31] = 5;
+    huff_build(&c->dist, lengths, 32);
+    return inflate_block_codes(r, o, &c->lit, &c->dist);
 }
 
-static int inflate_dynamic(bit_reader *r, out_window *o) {
-    static const int order[19] = {16, 17, 18, 0, 8, 7, 9, 6, 10, 5,
-                                  11, 4, 12, 3, 13, 2, 14, 1, 15};
-    int lengths[320], nlen, ndist, ncode, index, left, st;
+/* A block with dynamic codes (RFC 1951 section 3.2.7): HLIT, HDIST and
+ * HCLEN, the code lengths of the code-length alphabet in its fixed order,
+ * then the HLIT + HDIST literal/length and distance code lengths as one
+ * sequence coded with that alphabet (16 repeats the previous length 3-6
+ * times, 17 and 18 give runs of 3-10 and 11-138 zeros). */
+static int inflate_dynamic(bit_reader *r, out_window *o, code_set *c) {
+    static const int clen_order[19] = {16, 17, 18, 0, 8, 7, 9, 6, 10, 5,
+                                       11, 4, 12, 3, 13, 2, 14, 1, 15};
+    int clen_lengths[19], lengths[286 + 30], hlit, hdist, hclen, filled, i, st;
     uint32_t x;
-    huffman lencode, lit, dist;
 
     st = bits(r, 5, &x);
     if (st) return st;
-    nlen = (int)x + 257;
+    hlit = (int)x + 257;
     st = bits(r, 5, &x);
     if (st) return st;
-    ndist = (int)x + 1;
+    hdist = (int)x + 1;
     st = bits(r, 4, &x);
     if (st) return st;
-    ncode = (int)x + 4;
-    if (nlen > 286 || ndist > 30) return ORACLE_E_CORRUPT;
+    hclen = (int)x + 4;
+    if (hlit > 286 || hdist > 30) return ORACLE_E_CORRUPT;
 
-    for (index = 0; index < 19; index++) lengths[index] = 0;
-    for (index = 0; index < ncode; index++) {
+    for (i = 0; i < 19; i++) clen_lengths[i] = 0;
+    for (i = 0; i < hclen; i++) {
         st = bits(r, 3, &x);
         if (st) return st;
-        lengths[order[index]] = (int)x;
+        clen_lengths[clen_order[i]] = (int)x;
     }
-    left = huff_build(&lencode, lengths, 19);
-    if (left != 0) return ORACLE_E_CORRUPT; /* code-length code must be complete */
+    huff_build(&c->clen, clen_lengths, 19);
+    /* The code-length code must be complete. */
+    if (c->clen.kraft != (1L << 15)) return ORACLE_E_CORRUPT;
 
-    index = 0;
-    while (index < nlen + ndist) {
-        int sym, len = 0, rep;
-        st = huff_decode(r, &lencode, &sym);
+    filled = 0;
+    while (filled < hlit + hdist) {
+        int sym, value, repeat;
+        st = huff_decode(r, &c->clen, &sym);
         if (st) return st;
-        if (sym < 16) {
-            lengths[index++] = sym;
+        if (sym <= 15) {
+            lengths[filled++] = sym;
             continue;
         }
         if (sym == 16) {
-            if (index == 0) return ORACLE_E_CORRUPT;
-            len = lengths[index - 1];
+            if (filled == 0) return ORACLE_E_CORRUPT; /* nothing to repeat */
+            value = lengths[filled - 1];
             st = bits(r, 2, &x);
-            if (st) return st;
-            rep = 3 + (int)x;
+            repeat = 3 + (int)x;
         } else if (sym == 17) {
+            value = 0;
             st = bits(r, 3, &x);
-            if (st) return st;
-            rep = 3 + (int)x;
+            repeat = 3 + (int)x;
         } else {
+            value = 0;
             st = bits(r, 7, &x);
-            if (st) return st;
-            rep = 11 + (int)x;
+            repeat = 11 + (int)x;
         }
-        if (index + rep > nlen + ndist) return ORACLE_E_CORRUPT;
-        while (rep--) lengths[index++] = len;
+        if (st) return st;
+        if (filled + repeat > hlit + hdist) return ORACLE_E_CORRUPT;
+        for (i = 0; i < repeat; i++) lengths[filled++] = value;
     }
     if (lengths[256] == 0) return ORACLE_E_CORRUPT; /* no end-of-block code */
 
-    left = huff_build(&lit, lengths, nlen);
-    if (!huff_usable(&lit, left, 0)) return ORACLE_E_CORRUPT;
-    left = huff_build(&dist, lengths + nlen, ndist);
-    if (!huff_usable(&dist, left, 1)) return ORACLE_E_CORRUPT;
-    {
-        int any = 0, len;
-        for (len = 1; len < 16; len++) any |= dist.count[len];
-        return inflate_codes(r, o, &lit, &dist, any != 0);
-    }
+    huff_build(&c->lit, lengths, hlit);
+    if (!huff_usable(&c->lit, 0)) return ORACLE_E_CORRUPT;
+    huff_build(&c->dist, lengths + hlit, hdist);
+    if (!huff_usable(&c->dist, 1)) return ORACLE_E_CORRUPT;
+    return inflate_block_codes(r, o, &c->lit, &c->dist);
 }
 
+/* The blocks of one raw Deflate stream (RFC 1951 section 3.2.3): BFINAL,
+ * BTYPE, the block; after the final block the output must be full. */
 static int decode_deflate(const uint8_t *in, uint64_t in_len, uint8_t *out,
-                          uint64_t cap, uint64_t *n_out) {
+                          uint64_t cap, uint64_t *n_out, code_set *c) {
     bit_reader r = {in, 8 * in_len, 0};
     out_window o = {out, cap, 0};
     int st = ORACLE_OK;
@@ -597,9 +625,9 @@ static int decode_deflate(const uint8_t *in, uint64_t in_len, uint8_t *out,
         if (type == 0)
             st = inflate_stored(&r, &o);
         else if (type == 1)
-            st = inflate_fixed(&r, &o);
+            st = inflate_fixed(&r, &o, c);
         else if (type == 2)
-            st = inflate_dynamic(&r, &o);
+            st = inflate_dynamic(&r, &o, c);
         else
             st = ORACLE_E_CORRUPT;
         if (st) break;
@@ -612,12 +640,27 @@ static int decode_deflate(const uint8_t *in, uint64_t in_len, uint8_t *out,
     return st;
 }
 
+/* A key table per code for a decode call, all entries -1. */
+static int code_set_init(code_set *c) {
+    int16_t *t = (int16_t *)malloc(3 * sizeof(int16_t) * HUFF_KEYS);
+    if (!t) return -1;
+    memset(t, 0xff, 3 * sizeof(int16_t) * HUFF_KEYS);
+    memset(c, 0, sizeof(*c));
+    c->lit.symbol_of = t;
+    c->dist.symbol_of = t + HUFF_KEYS;
+    c->clen.symbol_of = t + 2 * HUFF_KEYS;
+    return 0;
+}
+
+static void code_set_free(code_set *c) { free(c->lit.symbol_of); }
+
 /* ------------------------------------------------------------------ */
 /* Entry points                                                         */
 /* ------------------------------------------------------------------ */
 
-int oracle_decode_chunk(int codec, const uint8_t *in, uint64_t in_len,
-                        uint8_t *out, uint64_t out_cap, uint64_t *produced) {
+/* One chunk; c holds the Huffman key table for Deflate (NULL otherwise). */
+static int decode_one_chunk(int codec, const uint8_t *in, uint64_t in_len, uint8_t *out,
+                            uint64_t out_cap, uint64_t *produced, code_set *c) {
     uint64_t n = 0;
     int st;
     *produced = 0;
@@ -631,12 +674,24 @@ int oracle_decode_chunk(int codec, const uint8_t *in, uint64_t in_len,
         *produced = n * 8;
         return st;
     }
-    if (codec == ORACLE_DEFLATE) {
-        st = decode_deflate(in, in_len, out, out_cap, &n);
+    if (codec == ORACLE_DEFLATE && c) {
+        st = decode_deflate(in, in_len, out, out_cap, &n, c);
         *produced = n;
         return st;
     }
     return ORACLE_E_INVALID_ARGUMENT;
+}
+
+int oracle_decode_chunk(int codec, const uint8_t *in, uint64_t in_len,
+                        uint8_t *out, uint64_t out_cap, uint64_t *produced) {
+    code_set c;
+    int st;
+    *produced = 0;
+    if (codec != ORACLE_DEFLATE) return decode_one_chunk(codec, in, in_len, out, out_cap, produced, NULL);
+    if (code_set_init(&c)) return ORACLE_E_INVALID_ARGUMENT;
+    st = decode_one_chunk(codec, in, in_len, out, out_cap, produced, &c);
+    code_set_free(&c);
+    return st;
 }
 
 int oracle_decompress(int codec, const uint8_t *comp,
@@ -644,19 +699,23 @@ int oracle_decompress(int codec, const uint8_t *comp,
                       const uint64_t *out_offsets, uint64_t n_chunks,
                       int32_t *status) {
     uint64_t i;
+    code_set c;
     if (codec < ORACLE_RLE_V1 || codec > ORACLE_DEFLATE) return -1;
     if (n_chunks && (!comp || !chunk_offsets || !out || !out_offsets)) return -1;
+    if (codec == ORACLE_DEFLATE && code_set_init(&c)) return -1;
     for (i = 0; i < n_chunks; i++) {
         uint64_t produced;
         int st;
         if (chunk_offsets[i + 1] < chunk_offsets[i] || out_offsets[i + 1] < out_offsets[i])
             st = ORACLE_E_INVALID_ARGUMENT;
         else
-            st = oracle_decode_chunk(codec, comp + chunk_offsets[i],
-                                     chunk_offsets[i + 1] - chunk_offsets[i],
-                                     out + out_offsets[i],
-                                     out_offsets[i + 1] - out_offsets[i], &produced);
+            st = decode_one_chunk(codec, comp + chunk_offsets[i],
+                                  chunk_offsets[i + 1] - chunk_offsets[i],
+                                  out + out_offsets[i],
+                                  out_offsets[i + 1] - out_offsets[i], &produced,
+                                  codec == ORACLE_DEFLATE ? &c : NULL);
         if (status) status[i] = st;
     }
+    if (codec == ORACLE_DEFLATE) code_set_free(&c);
     return 0;
 }
