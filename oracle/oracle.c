@@ -270,7 +270,7 @@ static int decode_rle_v2(const uint8_t *in, uint64_t in_len, uint8_t *out,
             pgw = (b3 >> 5) + 1;
             pll = b3 & 31;
             ew = orc_closest_width(pgw + pw);
-            if (w + pw > 64 || ew == 0) { st = ORACLE_E_CORRUPT; goto done; }
+            if (ew == 0) { st = ORACLE_E_CORRUPT; goto done; } /* gap + patch over 64 bits */
             if (n + len > cap_values) { st = ORACLE_E_OVERFLOW; goto done; }
             st = br_be(&r, bw, &base_raw);
             if (st) goto done;
@@ -292,7 +292,7 @@ static int decode_rle_v2(const uint8_t *in, uint64_t in_len, uint8_t *out,
                 cursor += gap;
                 if (gap == 255 && patch == 0) continue; /* filler entry */
                 if (cursor >= len) { st = ORACLE_E_CORRUPT; goto done; }
-                vals[cursor] |= patch << w;
+                if (w < 64) vals[cursor] |= patch << w; /* bits past 63 are dropped */
             }
             for (k = 0; k < len; k++) put_i64(out, n + k, (uint64_t)base + vals[k]);
             n += len;

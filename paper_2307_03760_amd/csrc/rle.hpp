@@ -320,9 +320,11 @@ __device__ __forceinline__ int rle_v2_short_repeats(InRing &in, uint32_t &pos, u
         if (s < kWave) {
             // Stopped at a lane that does not continue the chain: a
             // SHORT_REPEAT header inside the input there has its value cut
-            // off; any other header is handed back.
+            // off; any other header is handed back.  With the output already
+            // full nothing more is parsed: the caller reports the bytes left
+            // over.
             int st = CODAG_OK;
-            if (pos + s < end) {
+            if (pos + s < end && n < cap) {
                 const uint32_t hs = readlane(h, s);
                 if ((hs >> 6) == 0)
                     st = n + (hs & 7) + 3 > cap ? CODAG_E_OVERFLOW : CODAG_E_TRUNCATED;
@@ -418,7 +420,7 @@ __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t
             uint32_t bw = (b2 >> 5) + 1, pw = orc_width(b2 & 31);
             uint32_t pgw = (b3 >> 5) + 1, pll = b3 & 31;
             uint32_t ew = orc_fit_width(pgw + pw);
-            if (w + pw > 64 || ew == 0) return CODAG_E_CORRUPT;
+            if (ew == 0) return CODAG_E_CORRUPT;  // gap + patch entries over 64 bits
             if (n + len > cap) return CODAG_E_OVERFLOW;
             uint32_t bsec = pos + 4;
             if (bsec + bw > end) return CODAG_E_TRUNCATED;
@@ -462,6 +464,11 @@ __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t
             // Patch j lands on value cursor[j] (below 2^13: at most 31
             // gaps below 2^8).  A filler entry's patch is zero, so OR-ing it
             // in changes nothing and needs no test.
+            // Patch bits shifted past bit 63 are dropped (the data width
+            // plus the patch width may exceed 64; with a 64-bit data width
+            // a patch changes nothing).
+            if (w >= 64) patch = 0;
+            else patch <<= w;
             const uint32_t cur = (uint32_t)cursor, plo = (uint32_t)patch, phi = (uint32_t)(patch >> 32);
             uint32_t jp = 0;
             if (whole && w <= 32) {
@@ -482,7 +489,7 @@ __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t
                         const uint32_t pj = readlane(cur, jp);
                         if (pj >= i0 + kWave) break;
                         const uint64_t pt = ((uint64_t)readlane(phi, jp) << 32) | readlane(plo, jp);
-                        if (i == pj) v |= pt << w;
+                        if (i == pj) v |= pt;
                         jp++;
                     }
                     if (i < len) out[n + i] = base + v;
@@ -499,7 +506,7 @@ __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t
                     const uint32_t pj = readlane(cur, jp);
                     if (pj >= i0 + kWave) break;
                     const uint64_t pt = ((uint64_t)readlane(phi, jp) << 32) | readlane(plo, jp);
-                    if (i == pj) v |= pt << w;
+                    if (i == pj) v |= pt;
                     jp++;
                 }
                 if (i < len) out[n + i] = base + v;

@@ -89,3 +89,49 @@ def integer_data_streams(path: str, column: int = 1):
     if len(kinds) != 1:
         raise ValueError("mixed encodings across stripes")
     return kinds.pop(), out
+
+
+# ORC RLE v2 width codes (5-bit code -> bits), as the format defines them.
+V2_WIDTHS = [c + 1 for c in range(24)] + [26, 28, 30, 32, 40, 48, 56, 64]
+
+
+def _closest_width(n: int) -> int:
+    return next(w for w in V2_WIDTHS if w >= n)
+
+
+def _varint_end(buf: bytes, i: int) -> int:
+    while buf[i] & 0x80:
+        i += 1
+    return i + 1
+
+
+def rle_v2_width_codes(stream: bytes):
+    """Walk the run headers of an RLE v2 stream (skipping payloads) and
+    return the width codes it uses as widths: DIRECT and PATCHED_BASE data
+    widths, PATCHED_BASE patch widths, and DELTA widths other than the fixed
+    code 0.  Raises if the runs do not end exactly at the end of the stream."""
+    codes, i = [], 0
+    while i < len(stream):
+        h = stream[i]
+        kind = h >> 6
+        if kind == 0:
+            i += 2 + ((h >> 3) & 7)
+            continue
+        code = (h >> 1) & 31
+        n = (((h & 1) << 8) | stream[i + 1]) + 1
+        if kind == 1:
+            codes.append(code)
+            i += 2 + (n * V2_WIDTHS[code] + 7) // 8
+        elif kind == 2:
+            b2, b3 = stream[i + 2], stream[i + 3]
+            pw, pgw, pll = V2_WIDTHS[b2 & 31], (b3 >> 5) + 1, b3 & 31
+            codes += [code, b2 & 31]
+            i += 4 + (b2 >> 5) + 1 + (n * V2_WIDTHS[code] + 7) // 8 + (pll * _closest_width(pgw + pw) + 7) // 8
+        else:
+            if code:
+                codes.append(code)
+            j = _varint_end(stream, _varint_end(stream, i + 2))
+            i = j + (max(n - 2, 0) * (V2_WIDTHS[code] if code else 0) + 7) // 8
+    if i != len(stream):
+        raise ValueError("runs do not end at the end of the stream")
+    return codes

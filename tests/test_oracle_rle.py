@@ -100,6 +100,49 @@ def test_orc_writer_emits_every_v2_subencoding():
     assert seen == {0, 1, 2, 3}
 
 
+def width_code_cases():
+    """Columns for which the Apache ORC writer (through pyarrow) emits, over
+    all of them, every one of the 32 RLE v2 width codes: random values of
+    each zigzag bit width (DIRECT at the byte-aligned widths), monotone
+    columns with steps of each width (DELTA), values of each width with 3%
+    large outliers (PATCHED_BASE data and patch widths at every code) and
+    {0, -1} with outliers (width 1)."""
+    rng = np.random.default_rng(2024)
+    cols = []
+    for b in range(1, 65):
+        lo, hi = 1 << (b - 1), (1 << b) - 1
+        z = rng.integers(lo, hi, 512, dtype=np.uint64, endpoint=True)
+        cols.append(((z >> np.uint64(1)).astype(np.int64)) ^ (-(z & np.uint64(1)).astype(np.int64)))
+    for b in range(1, 63):
+        steps = rng.integers(1 << (b - 1), (1 << b) - 1, 512, endpoint=True)
+        cols.append(np.cumsum(steps // 2 if b > 60 else steps).astype(np.int64))
+    for b in range(1, 58):
+        for _ in range(3):
+            base = rng.integers(0, 1 << b, 512) | (1 << (b - 1))
+            top = min(63, b + 1 + int(rng.integers(1, 62 - b + 1)))
+            cols.append(np.where(rng.random(512) < 0.03,
+                                 rng.integers(1 << (top - 1), (1 << top) - 1, 512), base).astype(np.int64))
+    cols.append(np.where(rng.random(512) < 0.03, rng.integers(1 << 20, 1 << 30, 512),
+                         -rng.integers(0, 2, 512)).astype(np.int64))
+    return cols
+
+
+def test_every_width_code_from_orc_writer():
+    """All 32 RLE v2 width codes occur, as widths, in streams the Apache ORC
+    writer produced, and the oracle decodes every one of those streams to the
+    column that was written."""
+    from orc_walk import rle_v2_width_codes
+    seen = set()
+    for vals in width_code_cases():
+        kind, streams = _orc_roundtrip(vals, "0.12")
+        assert kind == 2 and len(streams) == 1
+        seen.update(rle_v2_width_codes(streams[0]))
+        st, out = decode(oracle.RLE_V2, streams[0], vals.size)
+        assert st == oracle.OK
+        np.testing.assert_array_equal(out, vals)
+    assert seen == set(range(32)), sorted(set(range(32)) - seen)
+
+
 def test_patched_base_filler_entries_from_orc_writer():
     """Gaps over 255 between outliers are written as (255, 0) filler entries."""
     vals = np.zeros(512, dtype=np.int64) + np.arange(512) % 4000
