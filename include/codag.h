@@ -118,19 +118,23 @@ int codag_decompress_ex(int codec, const uint8_t *comp_buf, const uint64_t *chun
                         void *stream, int32_t *chunk_status, const codag_opts *opts);
 
 /*
- * Synchronize `stream`, then return the status of the lowest-indexed chunk
- * that failed in any call on the current device since the previous
- * codag_get_error (CODAG_OK if none), storing that chunk's index in
- * *first_bad_chunk (may be NULL; UINT64_MAX if none).  Clears the error word.
- * Returns CODAG_E_HIP if synchronization or the read fails.
+ * Return the status of the lowest-indexed chunk that failed in any call on
+ * the current device since the previous codag_get_error (CODAG_OK if none),
+ * storing that chunk's index in *first_bad_chunk (may be NULL; UINT64_MAX if
+ * none), and clear the error word.  The read-and-clear is one atomic
+ * exchange enqueued on `stream` after its pending work; the call then
+ * synchronizes `stream`.  A failure recorded concurrently by work on another
+ * stream is either returned here or kept for the next call, never lost.
+ * Returns CODAG_E_HIP if the launch, the copy or the synchronization fails.
  */
 int codag_get_error(void *stream, uint64_t *first_bad_chunk);
 
 /* A static, human-readable name for a status code. */
 const char *codag_status_string(int status);
 
-/* Release the library's per-device resources (error words).  Any later call
- * re-creates them. */
+/* Forget the library's per-device state (the looked-up address of its
+ * static error word; it allocates no device memory of its own outside
+ * plans).  Any later call looks it up again. */
 void codag_shutdown(void);
 
 

@@ -44,6 +44,19 @@ __global__ void __launch_bounds__(kWave * WPB)
 
 namespace codag {
 
+// The per-device first-error word, (chunk << 4) | -status of the smallest
+// failing chunk, all ones when there is none; and the slot codag_get_error's
+// exchange writes the taken value to.  Device globals, so the library
+// allocates nothing for them; each device holds its own copy.
+__device__ unsigned long long g_error_word[2] = {~0ull, ~0ull};
+
+// Takes the error word and leaves "no error" in one atomic step, so a
+// failure recorded by a kernel on another stream is either taken here or
+// stays for the next call.
+__global__ void take_error(unsigned long long *word) {
+    if (threadIdx.x == 0) word[1] = atomicExch(&word[0], ~0ull);
+}
+
 std::mutex g_mu;
 DeviceState g_dev[kMaxDevices];
 
@@ -53,14 +66,9 @@ int device_state(DeviceState **out) {
     std::lock_guard<std::mutex> lock(g_mu);
     DeviceState &s = g_dev[dev];
     if (!s.err) {
-        unsigned long long *p = nullptr;
-        if (hipMalloc(&p, sizeof(*p)) != hipSuccess) return CODAG_E_HIP;
-        unsigned long long none = ~0ull;
-        if (hipMemcpy(p, &none, sizeof(none), hipMemcpyHostToDevice) != hipSuccess) {
-            (void)hipFree(p);
-            return CODAG_E_HIP;
-        }
-        s.err = p;
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_error_word)) != hipSuccess || !p) return CODAG_E_HIP;
+        s.err = static_cast<unsigned long long *>(p);
     }
     *out = &s;
     return CODAG_OK;
@@ -145,7 +153,7 @@ int codag_decompress_ex(int codec, const uint8_t *comp_buf, const uint64_t *chun
             const int gp = opts ? opts->group_parallel : 0;
             if (gp == 2 || (gp == 0 && !ticks && n_chunks <= kSplitMaxChunks))
                 return launch_rle_v1_split(comp_buf, chunk_offsets, out_buf, out_offsets,
-                                           (uint32_t)n_chunks, chunk_status, ds->err, s);
+                                           (uint32_t)n_chunks, chunk_status, ds->err, s, nullptr);
         }
             return launch_plain<CODAG_RLE_V1, 10, 0>(comp_buf, chunk_offsets, out_buf, out_offsets,
                                                      n_chunks, wpb, chunk_status, ds->err, ticks, s);
@@ -173,11 +181,19 @@ int codag_get_error(void *stream, uint64_t *first_bad_chunk) {
     DeviceState *ds = nullptr;
     int st = device_state(&ds);
     if (st) return st;
-    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return CODAG_E_HIP;
-    unsigned long long key = 0, none = ~0ull;
-    if (hipMemcpy(&key, ds->err, sizeof(key), hipMemcpyDeviceToHost) != hipSuccess) return CODAG_E_HIP;
-    if (key == none) return CODAG_OK;
-    if (hipMemcpy(ds->err, &none, sizeof(none), hipMemcpyHostToDevice) != hipSuccess) return CODAG_E_HIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned long long key = ~0ull;
+    {
+        // One taker at a time per process: the result slot is shared.
+        static std::mutex take_mu;
+        std::lock_guard<std::mutex> lock(take_mu);
+        hipLaunchKernelGGL(take_error, dim3(1), dim3(64), 0, s, ds->err);
+        if (hipGetLastError() != hipSuccess) return CODAG_E_HIP;
+        if (hipMemcpyAsync(&key, ds->err + 1, sizeof(key), hipMemcpyDeviceToHost, s) != hipSuccess)
+            return CODAG_E_HIP;
+        if (hipStreamSynchronize(s) != hipSuccess) return CODAG_E_HIP;
+    }
+    if (key == ~0ull) return CODAG_OK;
     if (first_bad_chunk) *first_bad_chunk = key >> 4;
     return -(int)(key & 15);
 }
@@ -196,13 +212,9 @@ const char *codag_status_string(int status) {
 }
 
 void codag_shutdown(void) {
+    // Nothing is allocated per device; forget the looked-up addresses.
     std::lock_guard<std::mutex> lock(g_mu);
-    for (auto &s : g_dev) {
-        if (s.err) {
-            (void)hipFree(s.err);
-            s.err = nullptr;
-        }
-    }
+    for (auto &s : g_dev) s = DeviceState{};
 }
 
 }  // extern "C"

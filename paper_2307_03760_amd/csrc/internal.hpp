@@ -14,7 +14,7 @@ namespace codag {
 constexpr int kMaxDevices = 64;
 
 struct DeviceState {
-    unsigned long long *err = nullptr;  // first-error word: (chunk << 4) | -status
+    unsigned long long *err = nullptr;  // first-error word: (chunk << 4) | -status, then a result slot
 };
 
 extern std::mutex g_mu;
@@ -24,10 +24,16 @@ extern DeviceState g_dev[kMaxDevices];
 int device_state(DeviceState **out);
 
 // Group-parallel RLE v1 (few chunks): index, decode and status passes on s.
+// The passes share a device workspace of rle_v1_split_workspace(n) bytes
+// (every byte written before it is read, so it needs no clearing): the
+// caller's, or with workspace == NULL one from the stream-ordered allocator.
 int launch_rle_v1_split(const uint8_t *comp, const uint64_t *coff, uint8_t *out,
                         const uint64_t *ooff, uint32_t n, int32_t *status, unsigned long long *err,
-                        hipStream_t s);
+                        hipStream_t s, void *workspace);
+size_t rle_v1_split_workspace(uint32_t n);
 constexpr uint64_t kSplitMaxChunks = 256;
+// Per chunk: 16 range records of 16 bytes and two 8-byte error keys.
+constexpr size_t kSplitWorkspacePerChunk = 16 * 16 + 2 * 8;
 
 // Arguments of one batched launch (a captured graph is reused while they
 // stay the same).

@@ -225,15 +225,20 @@ __global__ void rle_v1_finish(uint32_t n, const unsigned long long *keys, int32_
     if (st != CODAG_OK) atomicMin(err, (unsigned long long)error_key(c, st));
 }
 
+size_t rle_v1_split_workspace(uint32_t n) {
+    return (size_t)n * kSplitWorkspacePerChunk;
+}
+
 int launch_rle_v1_split(const uint8_t *comp, const uint64_t *coff, uint8_t *out,
                         const uint64_t *ooff, uint32_t n, int32_t *status, unsigned long long *err,
-                        hipStream_t s) {
-    // Workspace from the stream-ordered allocator: concurrent launches on
-    // other streams get their own.
+                        hipStream_t s, void *workspace) {
+    static_assert(kSplitWorkspacePerChunk == kSplitWaves * sizeof(uint4) + 2 * sizeof(unsigned long long),
+                  "workspace layout");
+    // Without a caller's workspace it comes from the stream-ordered
+    // allocator, so concurrent launches on other streams get their own.
     const size_t range_bytes = (size_t)n * kSplitWaves * sizeof(uint4);
-    const size_t bytes = range_bytes + (size_t)n * 2 * sizeof(unsigned long long);
-    void *ws = nullptr;
-    if (hipMallocAsync(&ws, bytes, s) != hipSuccess) return CODAG_E_HIP;
+    void *ws = workspace;
+    if (!ws && hipMallocAsync(&ws, rle_v1_split_workspace(n), s) != hipSuccess) return CODAG_E_HIP;
     uint4 *range = static_cast<uint4 *>(ws);
     unsigned long long *keys =
         reinterpret_cast<unsigned long long *>(static_cast<char *>(ws) + range_bytes);
@@ -244,8 +249,8 @@ int launch_rle_v1_split(const uint8_t *comp, const uint64_t *coff, uint8_t *out,
                        ooff, n, range, keys);
     hipLaunchKernelGGL(rle_v1_finish, dim3((n + 255) / 256), dim3(256), 0, s, n, keys, status, err);
     hipError_t e = hipGetLastError();
-    if (hipFreeAsync(ws, s) != hipSuccess || e != hipSuccess) return CODAG_E_HIP;
-    return CODAG_OK;
+    if (!workspace && hipFreeAsync(ws, s) != hipSuccess) return CODAG_E_HIP;
+    return e == hipSuccess ? CODAG_OK : CODAG_E_HIP;
 }
 
 }  // namespace codag

@@ -204,6 +204,23 @@ def test_capacity_statuses(dev):
     assert st.tolist() == [0, oracle.E_OVERFLOW, oracle.E_UNDERFLOW, oracle.E_TRUNCATED, 0]
 
 
+def test_short_repeat_stretch_ending_at_capacity(dev):
+    """A stretch of SHORT_REPEAT runs that fills the output exactly, followed
+    by a header whose value is cut off by the end of the input: with the
+    output full nothing more is parsed and the leftover byte makes the chunk
+    CORRUPT; with room for one more value the cut-off header is an OVERFLOW
+    (capacity is checked before the payload), as in the sequential decode."""
+    runs = bytes([0x07, 0x0a]) * 3             # three runs of ten 5s (width 1)
+    blobs, sizes = [], []
+    for tail in (b"\x00", b"\x00\x02", b"\x40", b"\x07"):
+        for cap in (30, 31, 40):
+            blobs.append(runs + tail)
+            sizes.append(8 * cap)
+    ch = _chunks(oracle.RLE_V2, blobs, sizes)
+    st = assert_parity(oracle.RLE_V2, ch, dev)
+    assert st[0] == oracle.E_CORRUPT and st[1] == oracle.E_OVERFLOW
+
+
 # ---- corrupt inputs: same status class as the oracle -------------------------
 
 def _mutants(blobs, rng, count):

@@ -100,6 +100,60 @@ def test_adam_first_steps_closed_form():
         p = q
 
 
+def test_adam_varying_gradient_weighted_averages():
+    """Unrolling Adam's moment recursions (Kingma and Ba, Section 3) gives
+    m_t = (1 - b1) * sum_i b1^(t-i) g_i, whose weights sum to 1 - b1^t, so
+    the bias-corrected m_hat_t is the weighted average of g_1..g_t with
+    weights b1^(t-i); v_hat_t likewise averages g_i^2 with weights b2^(t-i).
+    With b1 = 1/2 and b2 = 3/4 and gradients that change every step, the
+    parameters after each step are checked against those averages; swapping
+    the two decay rates moves them far away."""
+    b1, b2, lr, eps = 0.5, 0.75, 0.1, 1e-8
+    gs = [np.array([1.0, -2.0, 0.5]), np.array([-1.0, 1.0, 0.5]),
+          np.array([3.0, 0.0, -0.25]), np.array([0.5, 4.0, 1.0])]
+    p0 = np.array([0.3, -0.7, 2.0])
+
+    def by_averages(dec1, dec2):
+        p = p0.copy()
+        out = []
+        for t in range(1, len(gs) + 1):
+            w1 = np.array([dec1 ** (t - i) for i in range(1, t + 1)])
+            w2 = np.array([dec2 ** (t - i) for i in range(1, t + 1)])
+            G = np.array(gs[:t])
+            m_hat = (w1[:, None] * G).sum(0) / w1.sum()
+            v_hat = (w2[:, None] * G * G).sum(0) / w2.sum()
+            p = p - lr * m_hat / (np.sqrt(v_hat) + eps)
+            out.append(p)
+        return out
+
+    expect = by_averages(b1, b2)
+    # Step 2 by hand for the first parameter: m_hat = (0.5 * 1 - 1) / 1.5 = -1/3,
+    # v_hat = (0.75 * 1 + 1) / 1.75 = 1, so it moves up by lr / 3.
+    assert expect[1][0] == pytest.approx(expect[0][0] + lr / 3, abs=1e-9)
+    p, m, v = p0.copy(), np.zeros(3), np.zeros(3)
+    for t, g in enumerate(gs, start=1):
+        p, m, v = mlp.adam_step(p, g, m, v, t, lr, b1=b1, b2=b2, eps=eps)
+        np.testing.assert_allclose(p, expect[t - 1], rtol=0, atol=1e-12)
+    swapped = by_averages(b2, b1)
+    assert np.abs(swapped[-1] - expect[-1]).max() > 1e-2
+
+
+def test_adam_without_momentum_is_rms_scaled():
+    """b1 = 0 leaves m_hat_t = g_t: each step is lr * g_t / (sqrt(v_hat_t) + eps)
+    with v_hat_t the b2-weighted average of the squared gradients."""
+    b2, lr = 0.6, 0.05
+    gs = [np.array([2.0, -1.0]), np.array([-1.0, 3.0]), np.array([0.5, 0.5])]
+    p, m, v = np.zeros(2), np.zeros(2), np.zeros(2)
+    sq = []
+    for t, g in enumerate(gs, start=1):
+        q, m, v = mlp.adam_step(p, g, m, v, t, lr, b1=0.0, b2=b2, eps=0.0)
+        sq.append(g * g)
+        w = np.array([b2 ** (t - i) for i in range(1, t + 1)])
+        v_hat = (w[:, None] * np.array(sq)).sum(0) / w.sum()
+        np.testing.assert_allclose(q - p, -lr * g / np.sqrt(v_hat), rtol=1e-12, atol=0)
+        p = q
+
+
 def _dynamic_stream(lit_lengths, dist_lengths, hclen=19):
     """A dynamic-block header written by hand: a complete code-length code
     (13 symbols of 4 bits, 6 of 5 bits), then every length sent literally."""

@@ -318,8 +318,17 @@ def _map(fn, items, nproc=None):
     if nproc <= 1 or len(items) < 64:
         return [fn(x) for x in items]
     ctx = mp.get_context("fork")
-    with ctx.Pool(nproc) as pool:
-        return pool.map(fn, items, chunksize=max(1, len(items) // (8 * nproc)))
+    pool = ctx.Pool(nproc)
+    try:
+        res = pool.map(fn, items, chunksize=max(1, len(items) // (8 * nproc)))
+        pool.close()
+    except BaseException:
+        pool.terminate()
+        raise
+    finally:
+        # Every worker has exited before the caller goes on.
+        pool.join()
+    return res
 
 
 # ---------------------------------------------------------------------------
