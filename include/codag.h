@@ -118,6 +118,25 @@ int codag_decompress_ex(int codec, const uint8_t *comp_buf, const uint64_t *chun
                         void *stream, int32_t *chunk_status, const codag_opts *opts);
 
 /*
+ * For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the same
+ * decode as codag_decompress_ex (same arguments, results and errors), but
+ * the call allocates nothing.  The one launch that needs a workspace, the
+ * group-parallel RLE v1 path (at most 256 RLE v1 chunks without chunk_ticks
+ * in the default mode, or any count with group_parallel = 2), takes it from
+ * a static per-device array of CODAG_NOALLOC_SCRATCH_BYTES bytes that the
+ * library holds on every device it runs on until the process ends; a launch
+ * needing more than that (group_parallel = 2 with more than 256 chunks)
+ * returns CODAG_E_INVALID_ARGUMENT.  Every call on one device shares that
+ * array: calls that overlap in time on one device (on different streams or
+ * threads) race and must not be made.
+ */
+#define CODAG_NOALLOC_SCRATCH_BYTES (256u * 272u)
+int codag_decompress_noalloc(int codec, const uint8_t *comp_buf, const uint64_t *chunk_offsets,
+                             uint8_t *out_buf, const uint64_t *out_offsets, uint64_t n_chunks,
+                             void *stream, int32_t *chunk_status, const struct codag_opts *opts);
+
+/*
  * Return the status of the lowest-indexed chunk that failed in any call on
  * the current device since the previous codag_get_error (CODAG_OK if none),
  * storing that chunk's index in *first_bad_chunk (may be NULL; UINT64_MAX if
@@ -132,9 +151,9 @@ int codag_get_error(void *stream, uint64_t *first_bad_chunk);
 /* A static, human-readable name for a status code. */
 const char *codag_status_string(int status);
 
-/* Forget the library's per-device state (the looked-up address of its
- * static error word; it allocates no device memory of its own outside
- * plans).  Any later call looks it up again. */
+/* Forget the library's per-device state (the looked-up addresses of its
+ * static error word and scratch array; it allocates no device memory of its
+ * own outside plans).  Any later call looks them up again. */
 void codag_shutdown(void);
 
 

@@ -56,6 +56,8 @@ def lib():
             L.codag_decompress.restype = i32
             L.codag_decompress_ex.argtypes = [i32, vp, vp, vp, vp, u64, vp, vp, ctypes.POINTER(Opts)]
             L.codag_decompress_ex.restype = i32
+            L.codag_decompress_noalloc.argtypes = [i32, vp, vp, vp, vp, u64, vp, vp, ctypes.POINTER(Opts)]
+            L.codag_decompress_noalloc.restype = i32
             L.codag_get_error.argtypes = [vp, ctypes.POINTER(u64)]
             L.codag_get_error.restype = i32
             L.codag_status_string.argtypes = [i32]
@@ -125,6 +127,12 @@ def decompress(codec: int, comp, chunk_offsets, out, out_offsets, *, status=None
     n_chunks + 1 offsets; out: uint8 device tensor; status: optional int32 device
     tensor of n_chunks; chunk_ticks: optional int64 device tensor of n_chunks.
     """
+    _decompress("codag_decompress_ex", codec, comp, chunk_offsets, out, out_offsets, status,
+                waves_per_block, lit_table_bits, history_kib, group_parallel, chunk_ticks, stream)
+
+
+def _decompress(entry, codec, comp, chunk_offsets, out, out_offsets, status, waves_per_block,
+                lit_table_bits, history_kib, group_parallel, chunk_ticks, stream):
     import torch
     n = chunk_offsets.numel() - 1
     if n < 0 or out_offsets.numel() != n + 1:
@@ -137,10 +145,20 @@ def decompress(codec: int, comp, chunk_offsets, out, out_offsets, *, status=None
     s = _check_dev(status, "status", (torch.int32,), n)
     t = _check_dev(chunk_ticks, "chunk_ticks", (torch.int64,), n)
     opts = Opts(waves_per_block, lit_table_bits, t, history_kib, group_parallel, (ctypes.c_int * 6)())
-    rc = lib().codag_decompress_ex(int(codec), a, b, c, d, n, _stream_handle(stream), s,
-                                   ctypes.byref(opts))
+    rc = getattr(lib(), entry)(int(codec), a, b, c, d, n, _stream_handle(stream), s,
+                               ctypes.byref(opts))
     if rc != OK:
-        raise CodagError(rc, "codag_decompress_ex")
+        raise CodagError(rc, entry)
+
+
+def decompress_noalloc(codec: int, comp, chunk_offsets, out, out_offsets, *, status=None,
+                       waves_per_block: int = 0, lit_table_bits: int = 0, history_kib: int = 0,
+                       group_parallel: int = 0, chunk_ticks=None, stream=None) -> None:
+    """Enqueue codag_decompress_noalloc (arguments as decompress()): the same
+    decode with every workspace in the library's static per-device scratch
+    array; calls that overlap in time on one device must not be made."""
+    _decompress("codag_decompress_noalloc", codec, comp, chunk_offsets, out, out_offsets, status,
+                waves_per_block, lit_table_bits, history_kib, group_parallel, chunk_ticks, stream)
 
 
 def get_error(stream=None):

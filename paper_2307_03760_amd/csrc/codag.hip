@@ -50,6 +50,14 @@ namespace codag {
 // allocates nothing for them; each device holds its own copy.
 __device__ unsigned long long g_error_word[2] = {~0ull, ~0ull};
 
+// Scratch memory of codag_decompress_noalloc: the group-parallel RLE v1
+// workspace for up to kSplitMaxChunks chunks, held by every device the
+// library runs on until the process ends.  Host code never uses this name
+// as an address: device_state looks up each device's copy once.
+constexpr size_t kNoAllocScratchBytes = kSplitMaxChunks * kSplitWorkspacePerChunk;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+static_assert(kNoAllocScratchBytes == CODAG_NOALLOC_SCRATCH_BYTES, "header limit");
+
 // Takes the error word and leaves "no error" in one atomic step, so a
 // failure recorded by a kernel on another stream is either taken here or
 // stays for the next call.
@@ -68,6 +76,9 @@ int device_state(DeviceState **out) {
     if (!s.err) {
         void *p = nullptr;
         if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_error_word)) != hipSuccess || !p) return CODAG_E_HIP;
+        void *q = nullptr;
+        if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) return CODAG_E_HIP;
+        s.scratch = q;
         s.err = static_cast<unsigned long long *>(p);
     }
     *out = &s;
@@ -123,11 +134,13 @@ int launch_deflate(const uint8_t *comp, const uint64_t *coff, uint8_t *out, cons
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-int codag_decompress_ex(int codec, const uint8_t *comp_buf, const uint64_t *chunk_offsets,
-                        uint8_t *out_buf, const uint64_t *out_offsets, uint64_t n_chunks,
-                        void *stream, int32_t *chunk_status, const codag_opts *opts) {
+// codag_decompress_ex, and with noalloc its variant that takes every
+// workspace from the device's static scratch array.
+int decompress(int codec, const uint8_t *comp_buf, const uint64_t *chunk_offsets, uint8_t *out_buf,
+               const uint64_t *out_offsets, uint64_t n_chunks, void *stream, int32_t *chunk_status,
+               const codag_opts *opts, bool noalloc) {
     if (codec != CODAG_RLE_V1 && codec != CODAG_RLE_V2 && codec != CODAG_DEFLATE)
         return CODAG_E_INVALID_ARGUMENT;
     if (n_chunks == 0) return CODAG_OK;
@@ -151,9 +164,13 @@ int codag_decompress_ex(int codec, const uint8_t *comp_buf, const uint64_t *chun
     switch (codec) {
         case CODAG_RLE_V1: {
             const int gp = opts ? opts->group_parallel : 0;
-            if (gp == 2 || (gp == 0 && !ticks && n_chunks <= kSplitMaxChunks))
+            if (gp == 2 || (gp == 0 && !ticks && n_chunks <= kSplitMaxChunks)) {
+                if (noalloc && rle_v1_split_workspace((uint32_t)n_chunks) > kNoAllocScratchBytes)
+                    return CODAG_E_INVALID_ARGUMENT;
                 return launch_rle_v1_split(comp_buf, chunk_offsets, out_buf, out_offsets,
-                                           (uint32_t)n_chunks, chunk_status, ds->err, s, nullptr);
+                                           (uint32_t)n_chunks, chunk_status, ds->err, s,
+                                           noalloc ? ds->scratch : nullptr);
+            }
         }
             return launch_plain<CODAG_RLE_V1, 10, 0>(comp_buf, chunk_offsets, out_buf, out_offsets,
                                                      n_chunks, wpb, chunk_status, ds->err, ticks, s);
@@ -167,6 +184,24 @@ int codag_decompress_ex(int codec, const uint8_t *comp_buf, const uint64_t *chun
             return launch_deflate<10>(comp_buf, chunk_offsets, out_buf, out_offsets, n_chunks, wpb,
                                       hist, chunk_status, ds->err, ticks, s);
     }
+}
+
+}  // namespace
+
+extern "C" {
+
+int codag_decompress_ex(int codec, const uint8_t *comp_buf, const uint64_t *chunk_offsets,
+                        uint8_t *out_buf, const uint64_t *out_offsets, uint64_t n_chunks,
+                        void *stream, int32_t *chunk_status, const codag_opts *opts) {
+    return decompress(codec, comp_buf, chunk_offsets, out_buf, out_offsets, n_chunks, stream,
+                      chunk_status, opts, false);
+}
+
+int codag_decompress_noalloc(int codec, const uint8_t *comp_buf, const uint64_t *chunk_offsets,
+                             uint8_t *out_buf, const uint64_t *out_offsets, uint64_t n_chunks,
+                             void *stream, int32_t *chunk_status, const codag_opts *opts) {
+    return decompress(codec, comp_buf, chunk_offsets, out_buf, out_offsets, n_chunks, stream,
+                      chunk_status, opts, true);
 }
 
 int codag_decompress(int codec, const uint8_t *comp_buf, const uint64_t *chunk_offsets,

@@ -15,6 +15,7 @@ constexpr int kMaxDevices = 64;
 
 struct DeviceState {
     unsigned long long *err = nullptr;  // first-error word: (chunk << 4) | -status, then a result slot
+    void *scratch = nullptr;            // this device's static scratch array
 };
 
 extern std::mutex g_mu;
