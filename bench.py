@@ -32,6 +32,8 @@ WORKLOADS = {
                "literal groups, seed 0", "int64"),
     "rle_v1_scaled": ("ORC integer RLE v1, 2^27 int64 values, 128 KiB chunks (8192), same "
                       "generator (scaled variant, not a listed configuration)", "int64"),
+    "rle_v2_scaled": ("ORC integer RLE v2, 2^28 int64 values, 256 KiB chunks (8192), same "
+                      "generator (scaled variant, not a listed configuration)", "int64"),
     "deflate": ("Deflate, 1 GiB in 64 KiB chunks (16384): 50% Zipf text, 30% int32 columns, "
                 "20% random bytes; zlib level 9, a third of compressible chunks fixed-Huffman, "
                 "seed 0", "u8"),
@@ -82,6 +84,8 @@ def make_workload(name: str):
         return workloads.rle_v1_workload(seed=0)
     if name == "rle_v1_scaled":
         return workloads.rle_v1_workload(seed=0, n_values=1 << 27)
+    if name == "rle_v2_scaled":
+        return workloads.rle_v2_workload(seed=0, n_values=1 << 28)
     if name == "deflate":
         return workloads.deflate_workload(seed=0)
     if name == "batched":
@@ -311,13 +315,14 @@ def time_workload(name, ch, steps, warmup, dev, flush_buf=None):
     return res, out
 
 
-def cpu_baseline(name, ch, gpu_out, budget_s):
-    """The oracle on a bounded sample of the workload's chunks, on the host's cores."""
+def cpu_baseline(name, ch, gpu_out, budget_s, threads=None):
+    """The oracle on a bounded sample of the workload's chunks, on `threads`
+    host threads (default: the host's share of cores)."""
     import numpy as np
     import oracle
     import workloads
     codec = int(ch.codecs[0])
-    threads = workloads.workers()
+    threads = threads or workloads.workers()
     n = ch.n_chunks
 
     def run(k):
@@ -361,10 +366,21 @@ def cpu_baseline(name, ch, gpu_out, budget_s):
         "cores": threads,
         "kind": "oracle",
         "sample": f"{k} of {n} chunks of the {name} workload ({int(oo[-1])} output bytes), "
-                  f"decoded {passes} time(s) by the plain C oracle on {threads} host threads "
+                  f"decoded {passes} time(s) by the plain C oracle on {threads} host thread(s) "
                   f"in {dt:.2f} s",
         "bit_exact_vs_gpu": exact,
     }
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():
@@ -373,9 +389,11 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rle_v2", choices=sorted(WORKLOADS))
-    ap.add_argument("--extras", default="rle_v1,deflate,batched,learned",
+    ap.add_argument("--extras", default="rle_v1,rle_v1_scaled,rle_v2_scaled,deflate,batched,learned",
                     help="comma-separated workloads also timed (empty for none)")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="oracle time for the headline baseline (the per-codec oracle timings "
+                         "under per_workload take a quarter of it per thread count)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--json-out", default="")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -429,6 +447,13 @@ def main():
             torch.cuda.empty_cache()
         else:
             r, o = time_workload(name, c2, args.steps, args.warmup, dev, flush)
+            if not args.no_cpu_baseline and name in ("rle_v1", "deflate"):
+                o_np = o.cpu().numpy()
+                r["cpu_oracle"] = {
+                    "threads_1": cpu_baseline(name, c2, o_np, args.cpu_seconds / 4, threads=1),
+                    "threads_T": cpu_baseline(name, c2, o_np, args.cpu_seconds / 4),
+                }
+                del o_np
             del o
         per[name] = r
         del c2
@@ -465,6 +490,10 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, ch, gpu_out_np, args.cpu_seconds)
+        one = cpu_baseline(args.workload, ch, gpu_out_np, args.cpu_seconds / 4, threads=1)
+        line["cpu_baseline"]["single_thread"] = {k: one[k] for k in ("value", "cores", "sample")}
+        line["cpu_baseline"]["cpu_model"] = cpu_model()
+        head["cpu_oracle"] = {"threads_1": one, "threads_T": line["cpu_baseline"]}
     print(json.dumps(line), flush=True)
     if args.json_out:
         with open(args.json_out, "w") as f:

@@ -55,15 +55,19 @@ enum {
  *                     With 32 the workgroup holds one wave.
  *   chunk_ticks       optional device array (n_chunks uint64): receives each
  *                     chunk's decode time in shader clock cycles.
- *   group_parallel    RLE v1 only: 0 = automatic (launches of at most 256
- *                     chunks without chunk_ticks are decoded group-parallel:
- *                     an index pass walks the runs and literal lists and
- *                     cuts them into 16 ranges of about equal output, then
- *                     16 waves per chunk decode one range each), 1 = one
- *                     wave per chunk, 2 = group-parallel (not with
- *                     chunk_ticks).  The group-parallel path takes its
- *                     workspace (272 bytes per chunk) from the
- *                     stream-ordered allocator (hipMallocAsync) on `stream`.
+ *   group_parallel    RLE codecs: 0 = automatic (RLE v1 launches of at
+ *                     most 256 chunks and RLE v2 launches of at most 2048
+ *                     chunks, without chunk_ticks, are decoded
+ *                     group-parallel), 1 = one wave per chunk,
+ *                     2 = group-parallel (not with chunk_ticks).
+ *                     Group-parallel: an index pass finds where the groups
+ *                     (RLE v1 runs and literal lists; RLE v2 runs) start,
+ *                     without decoding values, and cuts them into ranges of
+ *                     about equal output -- 16 per RLE v1 chunk, 8 per RLE
+ *                     v2 chunk -- then one wave per range decodes it.  The
+ *                     path takes its workspace (272 bytes per RLE v1 chunk,
+ *                     96 per RLE v2 chunk) from the stream-ordered allocator
+ *                     (hipMallocAsync) on `stream`.  Ignored for Deflate.
  */
 typedef struct codag_opts {
     int waves_per_block;
@@ -121,17 +125,18 @@ int codag_decompress_ex(int codec, const uint8_t *comp_buf, const uint64_t *chun
  * For callers that cannot allocate device memory -- code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc: the same
  * decode as codag_decompress_ex (same arguments, results and errors), but
- * the call allocates nothing.  The one launch that needs a workspace, the
- * group-parallel RLE v1 path (at most 256 RLE v1 chunks without chunk_ticks
- * in the default mode, or any count with group_parallel = 2), takes it from
- * a static per-device array of CODAG_NOALLOC_SCRATCH_BYTES bytes that the
- * library holds on every device it runs on until the process ends; a launch
- * needing more than that (group_parallel = 2 with more than 256 chunks)
+ * the call allocates nothing.  The launches that need a workspace, the
+ * group-parallel RLE paths (by default RLE v1 launches of at most 256
+ * chunks and RLE v2 launches of at most 2048 chunks, without chunk_ticks;
+ * any count with group_parallel = 2), take it from a static per-device
+ * array of CODAG_NOALLOC_SCRATCH_BYTES bytes that the library holds on every
+ * device it runs on until the process ends; a launch needing more than that
+ * (group_parallel = 2 with more than 722 RLE v1 or 2048 RLE v2 chunks)
  * returns CODAG_E_INVALID_ARGUMENT.  Every call on one device shares that
  * array: calls that overlap in time on one device (on different streams or
  * threads) race and must not be made.
  */
-#define CODAG_NOALLOC_SCRATCH_BYTES (256u * 272u)
+#define CODAG_NOALLOC_SCRATCH_BYTES (2048u * 96u)
 int codag_decompress_noalloc(int codec, const uint8_t *comp_buf, const uint64_t *chunk_offsets,
                              uint8_t *out_buf, const uint64_t *out_offsets, uint64_t n_chunks,
                              void *stream, int32_t *chunk_status, const struct codag_opts *opts);

@@ -50,11 +50,15 @@ namespace codag {
 // allocates nothing for them; each device holds its own copy.
 __device__ unsigned long long g_error_word[2] = {~0ull, ~0ull};
 
-// Scratch memory of codag_decompress_noalloc: the group-parallel RLE v1
-// workspace for up to kSplitMaxChunks chunks, held by every device the
-// library runs on until the process ends.  Host code never uses this name
-// as an address: device_state looks up each device's copy once.
-constexpr size_t kNoAllocScratchBytes = kSplitMaxChunks * kSplitWorkspacePerChunk;
+// Scratch memory of codag_decompress_noalloc: the workspace of the
+// group-parallel RLE paths at their default chunk limits (RLE v1: 256
+// chunks; RLE v2: 2048 chunks, the larger), held by every device the library
+// runs on until the process ends.  Host code never uses this name as an
+// address: device_state looks up each device's copy once.
+constexpr size_t kNoAllocScratchBytes =
+    kSplitMaxChunks * kSplitWorkspacePerChunk > kSplitV2MaxChunks * kSplitV2WorkspacePerChunk
+        ? kSplitMaxChunks * kSplitWorkspacePerChunk
+        : kSplitV2MaxChunks * kSplitV2WorkspacePerChunk;
 static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 static_assert(kNoAllocScratchBytes == CODAG_NOALLOC_SCRATCH_BYTES, "header limit");
 
@@ -174,7 +178,16 @@ int decompress(int codec, const uint8_t *comp_buf, const uint64_t *chunk_offsets
         }
             return launch_plain<CODAG_RLE_V1, 10, 0>(comp_buf, chunk_offsets, out_buf, out_offsets,
                                                      n_chunks, wpb, chunk_status, ds->err, ticks, s);
-        case CODAG_RLE_V2:
+        case CODAG_RLE_V2: {
+            const int gp = opts ? opts->group_parallel : 0;
+            if (gp == 2 || (gp == 0 && !ticks && n_chunks <= kSplitV2MaxChunks)) {
+                if (noalloc && rle_v2_split_workspace((uint32_t)n_chunks) > kNoAllocScratchBytes)
+                    return CODAG_E_INVALID_ARGUMENT;
+                return launch_rle_v2_split(comp_buf, chunk_offsets, out_buf, out_offsets,
+                                           (uint32_t)n_chunks, chunk_status, ds->err, s,
+                                           noalloc ? ds->scratch : nullptr);
+            }
+        }
             return launch_plain<CODAG_RLE_V2, 10, 0>(comp_buf, chunk_offsets, out_buf, out_offsets,
                                                      n_chunks, wpb, chunk_status, ds->err, ticks, s);
         default:

@@ -36,6 +36,17 @@ constexpr uint64_t kSplitMaxChunks = 256;
 // Per chunk: 16 range records of 16 bytes and two 8-byte error keys.
 constexpr size_t kSplitWorkspacePerChunk = 16 * 16 + 2 * 8;
 
+// Group-parallel RLE v2 (index pass, one decoding wave per range, status
+// pass), the same way; workspace rle_v2_split_workspace(n) bytes.
+int launch_rle_v2_split(const uint8_t *comp, const uint64_t *coff, uint8_t *out,
+                        const uint64_t *ooff, uint32_t n, int32_t *status, unsigned long long *err,
+                        hipStream_t s, void *workspace);
+size_t rle_v2_split_workspace(uint32_t n);
+constexpr uint64_t kSplitV2MaxChunks = 2048;
+// Per chunk: 8 range starts of 8 bytes, the stop value and padding (16
+// bytes), two 8-byte error keys.
+constexpr size_t kSplitV2WorkspacePerChunk = 8 * 8 + 16 + 2 * 8;
+
 // Arguments of one batched launch (a captured graph is reused while they
 // stay the same).
 struct BatchArgs {

@@ -310,7 +310,10 @@ __device__ __forceinline__ int rle_v2_short_repeats(InRing &in, uint32_t &pos, u
                 if (j + 1 < c) *reinterpret_cast<u64x2 *>(out + at + j) = vv;
             if (c & 1) out[at + c - 1] = v;
         }
-        if (fo < ff) return CODAG_E_OVERFLOW;
+        if (fo < ff) {
+            n = uni(readlane(at, fo));
+            return CODAG_E_OVERFLOW;
+        }
         if (ff < kWave) {
             n = cap;
             pos += ff;
@@ -339,9 +342,11 @@ __device__ __forceinline__ int rle_v2_short_repeats(InRing &in, uint32_t &pos, u
     }
 }
 
-__device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t cap) {
-    uint32_t pos = in.skip, end = in.gend;
-    uint32_t n = 0;
+// Runs from byte position pos, their first value being value n of the
+// chunk, until value cap.  On an error, n is the first value of the run that
+// failed.
+__device__ __forceinline__ int decode_rle_v2_runs(InRing &in, uint32_t &pos, uint32_t end,
+                                                  uint64_t *out, uint32_t &n, uint32_t cap) {
     const uint32_t l = lane();
     uint64_t x = 0;     // the header's first eight bytes
     bool have = false;  // x already read (handed back by a SHORT_REPEAT stretch)
@@ -593,7 +598,14 @@ __device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t
             n += len;
         }
     }
-    return pos == end ? CODAG_OK : CODAG_E_CORRUPT;
+    return CODAG_OK;
+}
+
+__device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t cap) {
+    uint32_t pos = in.skip, n = 0;
+    const int st = decode_rle_v2_runs(in, pos, in.gend, out, n, cap);
+    if (st) return st;
+    return pos == in.gend ? CODAG_OK : CODAG_E_CORRUPT;
 }
 
 }  // namespace codag

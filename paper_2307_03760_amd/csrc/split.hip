@@ -1,16 +1,15 @@
-// Group-parallel RLE v1 for launches with few chunks.
+// Group-parallel RLE v1 and v2 for launches with few chunks.
 //
-// With one wave per chunk, a launch of a few dozen chunks keeps a few dozen
-// SIMDs busy and each wave's decode is a long chain of dependent steps.
-// Here the chunk is decoded in two passes: an index pass (one wave per
-// chunk) walks the group headers -- runs fully, literal lists by counting
-// varint terminators without decoding them -- and cuts the groups into
-// kSplitWaves ranges of about equal output, recording where each range
-// starts in the input and in the output; then kSplitWaves waves per chunk
-// decode the ranges in parallel, each streaming through its own part of the
-// input.  A last pass combines, per chunk, the first error either pass saw
-// (errors are keyed by group index, so the earliest group wins, as in a
-// sequential decode).
+// With one wave per chunk, a launch of a few dozen (RLE v1) or a thousand
+// (RLE v2) chunks keeps at most one wave on each SIMD, and each wave's
+// decode is a long chain of dependent steps.  Here a chunk is decoded in
+// two passes: an index pass finds where the groups (runs) start -- without
+// decoding their values -- and cuts them into ranges of about equal output,
+// recording where each range starts in the input and in the output; then
+// one wave per range decodes the ranges in parallel, each streaming through
+// its own part of the input.  A last pass combines, per chunk, the first
+// error either pass saw (errors are keyed by stream position, so the
+// earliest group wins, as in a sequential decode).
 #include <hip/hip_runtime.h>
 
 #include "../../include/codag.h"
@@ -23,163 +22,229 @@ constexpr uint32_t kSplitWaves = 16;  // decoding waves per chunk
 constexpr int kSplitWpb = 4;          // decode pass: waves per block
 
 // With a few dozen waves on the chip each wave waits on every fetch it
-// makes, so the passes read their input in larger pieces than the one-wave
-// decoder: the index pass 8 KiB at a time (a chunk is a few dozen KiB), the
-// decode waves 4 KiB (each decodes a few KiB).
-using IndexRing = InRingT<8192>;
+// makes, so the decode waves read their input 4 KiB at a time (each decodes
+// a few KiB), more than the one-wave decoder's 1 KiB.
 using GroupRing = InRingT<4096>;
 
-// The index pass's view of the input: 512 bytes starting at w (8-aligned),
-// 8 per lane in registers.  Varint terminators (bytes with bit 7 clear) are
-// counted, per lane, as running counts in the bytes of c0 (bytes 0-3) and c1
-// (bytes 4-7), and over the wave as excl/incl (before / through this lane).
-// Headers are read with lane reads and literal lists are skipped by
-// counting terminators, so the serial walk touches LDS once per 512 bytes
-// and each group is one chain of lane reads and scalar instructions.
-struct IndexWindow {
-    uint32_t w, total;              // wave-uniform
-    uint32_t w0, w1, c0, c1, excl, incl;  // per lane
+// Index pass, one workgroup of kIdxWaves waves per chunk.  The chunk is
+// taken in windows of kIdxStep byte positions on a fixed grid.  For every
+// position p of a window the workgroup works out, in parallel, the group
+// that would start at p -- its length in bytes and in values, and what its
+// header and run base say about errors (runs), or where its last varint ends
+// (literal lists) -- from a count of varint terminator bytes (bit 7 clear)
+// over the window and a lookahead long enough for any valid group.  Then one
+// wave walks the real groups from where the previous window's walk left off,
+// one LDS read per group, and cuts them into kSplitWaves ranges of about
+// equal output.  Each window's bytes arrive by direct-to-LDS loads issued one
+// window ahead.
+constexpr uint32_t kIdxWaves = 8;
+constexpr uint32_t kIdxStep = 4096;                    // positions per window
+constexpr uint32_t kIdxAhead = 1536;                   // a valid group spans at most 1 + 10 * 128 bytes
+constexpr uint32_t kIdxRegion = kIdxStep + kIdxAhead;  // bytes read per window
+constexpr uint32_t kIdxPieces = kIdxRegion / 16;       // 16-byte loads per window
+static_assert(kIdxRegion % 16 == 0 && kIdxStep >= kIdxAhead, "window shape");
 
-    __device__ __forceinline__ void load(IndexRing &in, uint32_t at) {
-        w = at & ~7u;
-        in.ensure(w + 528);
-        const uint32_t wb = (w >> 2) + 2 * lane();
-        w0 = in.word(wb);
-        w1 = in.word(wb + 1);
-        // One per terminator byte; times 0x01010101 gives running counts.
-        c0 = ((~w0 & 0x80808080u) >> 7) * 0x01010101u;
-        c1 = ((~w1 & 0x80808080u) >> 7) * 0x01010101u + (c0 >> 24) * 0x01010101u;
-        incl = wave_inclusive_sum32(c1 >> 24);
-        excl = incl - (c1 >> 24);
-        total = readlane(incl, kWave - 1);
-    }
-    // Byte at x (inside the window).
-    __device__ __forceinline__ uint32_t byte(uint32_t x) const {
-        const uint32_t L = (x - w) >> 3, o = (x - w) & 7;
-        const uint32_t v = o < 4 ? readlane(w0, L) : readlane(w1, L);
-        return (v >> (8 * (o & 3))) & 0xff;
-    }
-    // Terminators in [w, x) (x inside the window).
-    __device__ __forceinline__ uint32_t before(uint32_t x) const {
-        const uint32_t L = (x - w) >> 3, o = (x - w) & 7;
-        const uint64_t cc = ((uint64_t)readlane(c1, L) << 32) | readlane(c0, L);
-        return readlane(excl, L) + (o ? (uint32_t)(cc >> (8 * o - 8)) & 0xff : 0);
-    }
-    // Position of terminator number k (1-based, k <= total): in the first
-    // lane whose count through it reaches k, the first byte whose running
-    // count reaches the rest (a bytewise compare; counts are at most 8, so
-    // no borrow crosses a byte).
-    __device__ __forceinline__ uint32_t nth(uint32_t k) const {
-        const uint32_t L = (uint32_t)__builtin_ctzll(ballot(incl >= k));
-        const uint64_t r = k - readlane(excl, L);
-        const uint64_t cc = ((uint64_t)readlane(c1, L) << 32) | readlane(c0, L);
-        const uint64_t ge = ((cc | 0x8080808080808080ull) - r * 0x0101010101010101ull) & 0x8080808080808080ull;
-        return w + 8 * L + ((uint32_t)__builtin_ctzll(ge) >> 3);
-    }
-};
+// Entry of a position: byte length (13 bits), value count (8 bits) and a
+// code: 0 = valid so far, 1 = truncated, 2 = corrupt (both for the header
+// and base of a run), 3 = a list whose end is not in the chunk.
+enum : uint32_t { kEntOk = 0, kEntTruncated = 1, kEntCorrupt = 2, kEntOpen = 3 };
+__device__ __forceinline__ uint32_t make_ent(uint32_t off, uint32_t len, uint32_t code) {
+    return off | (len << 13) | (code << 21);
+}
 
-// Index pass, one wave per chunk.  The groups it walks are cut into
-// kSplitWaves ranges of about equal output: range[c * kSplitWaves + j] =
-// (first group, end group, input position and first value of the first
-// group).  keys[2c] = the first structural error (group << 4 | -status), or
-// all ones; groups from that one on are in no range.
-__global__ void __launch_bounds__(kWave)
+__device__ __forceinline__ uint32_t lds_byte(const uint32_t *buf, uint32_t x) {
+    return (buf[x >> 2] >> (8 * (x & 3))) & 0xff;
+}
+
+// Index pass.  The groups are cut into kSplitWaves ranges of about equal
+// output: range[c * kSplitWaves + j] = (first group, end group, input
+// position and first value of the first group).  keys[2c] = the first
+// structural error (group << 4 | -status), or all ones; groups from that
+// one on are in no range.
+__global__ void __launch_bounds__(kWave * kIdxWaves)
     rle_v1_index(const uint8_t *comp, const uint64_t *coff, uint8_t *out, const uint64_t *ooff,
                  uint32_t n, uint4 *range, unsigned long long *keys) {
-    __shared__ __align__(16) uint32_t s_ring[IndexRing::kLdsWords];
-    __shared__ __align__(16) uint32_t s_land[IndexRing::kLand];
-    const uint32_t l = lane(), c = blockIdx.x;
+    __shared__ __align__(16) uint32_t s_buf[2][kIdxRegion / 4];
+    __shared__ uint16_t s_tcount[kIdxRegion];  // terminators before each region byte
+    __shared__ uint16_t s_tpos[kIdxRegion];    // region position of each terminator
+    __shared__ uint32_t s_ent[kIdxStep];
+    __shared__ uint32_t s_wsum[kIdxWaves];
+    __shared__ uint32_t s_done;
+    const uint32_t tid = threadIdx.x, wave = uni(tid / kWave), l = lane();
+    const uint32_t c = blockIdx.x;
     if (c >= n) return;
-    keys[2 * c + 1] = ~0ull;  // the decode pass's key, same value from every lane
+    if (tid == 0) keys[2 * c + 1] = ~0ull;  // the decode pass's key
     const uint64_t i0 = coff[c], i1 = coff[c + 1], o0 = ooff[c], o1 = ooff[c + 1];
     const uint32_t in_len = (uint32_t)(i1 - i0), out_len = (uint32_t)(o1 - o0);
     if ((((i1 - i0) | (o1 - o0)) >> 31) != 0 || (out_len & 7) ||
         (reinterpret_cast<uintptr_t>(out + o0) & 7)) {
-        if (l < kSplitWaves) range[(size_t)c * kSplitWaves + l] = make_uint4(0, 0, 0, 0);
-        keys[2 * c] = error_key(0, CODAG_E_INVALID_ARGUMENT);
+        if (tid < kSplitWaves) range[(size_t)c * kSplitWaves + tid] = make_uint4(0, 0, 0, 0);
+        if (tid == 0) keys[2 * c] = error_key(0, CODAG_E_INVALID_ARGUMENT);
         return;
     }
-    IndexRing in;
-    in.init(comp + i0, in_len, s_ring, s_land);
-    const uint32_t end = in.gend, cap = out_len / 8;
-    uint32_t pos = in.skip, nv = 0, k = 0;
-    // Lane j < kSplitWaves: the first group of range j and where it starts.
-    uint32_t rg = 0, rpos = 0, rnv = 0, j = 0;
-    uint32_t next = 0;  // first value at which range j starts
+    const uint8_t *chunk = comp + i0;
+    const uint32_t skip = (uint32_t)(reinterpret_cast<uintptr_t>(chunk) & 15);
+    const uint8_t *gbase = chunk - skip;  // positions are relative to the 16-byte hull
+    const uint32_t end = skip + in_len, cap = out_len / 8;
+
+    // Region of window t: bytes [t * kIdxStep, t * kIdxStep + kIdxRegion),
+    // one 1 KiB block of 16-byte loads per wave instruction.
+    auto issue = [&](uint32_t t) {
+        const uint32_t W = t * kIdxStep;
+        for (uint32_t b = wave; b * kWave < kIdxPieces; b += kIdxWaves) {
+            const uint32_t q = b * kWave + l, at = W + 16 * q;
+            if (q < kIdxPieces && at < end)
+                __builtin_amdgcn_global_load_lds(gbase + at, (lds_void *)(&s_buf[t & 1][b * 256]), 16, 0, 0);
+        }
+    };
+    issue(0);
+
+    // Walker state (wave 0, wave-uniform), and per lane j < kSplitWaves the
+    // first group of range j and where it starts.
+    uint32_t pos = skip, nv = 0, k = 0, j = 0, next = 0;
+    uint32_t rg = 0, rpos = 0, rnv = 0;
     unsigned long long key = ~0ull;
     bool open_end = false;
-    IndexWindow win;
-    win.load(in, pos);
-    while (nv < cap) {
-        if (pos >= end) {
-            key = error_key(k, CODAG_E_TRUNCATED);
-            break;
+
+    for (uint32_t t = 0;; t++) {
+        const uint32_t W = t * kIdxStep;
+        uint32_t *buf = s_buf[t & 1];
+        wait_vm();
+        __syncthreads();  // every wave's share of the region has landed
+        // Bytes past the end of the chunk read as zero (terminators).
+        for (uint32_t q = tid; q < kIdxPieces; q += kWave * kIdxWaves) {
+            const uint32_t at = W + 16 * q;
+            if (at + 16 > end) {
+                uint4 v = reinterpret_cast<uint4 *>(buf)[q];
+                const uint32_t valid = at < end ? end - at : 0;
+                uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const int keep = (int)valid - 4 * i;
+                    w[i] &= keep >= 4 ? 0xffffffffu : keep <= 0 ? 0u : ((1u << (8 * keep)) - 1);
+                }
+                reinterpret_cast<uint4 *>(buf)[q] = make_uint4(w[0], w[1], w[2], w[3]);
+            }
         }
-        if (pos + 16 > win.w + 512) win.load(in, pos);
-        const int32_t h = (int8_t)win.byte(pos);
-        const uint32_t gp = pos, gn = nv;
-        if (h >= 0) {
-            // Run: header, delta byte, base varint ending at terminator e.
-            const uint32_t len = (uint32_t)h + 3, x = pos + 2;
-            const uint32_t t = win.before(x) + 1;
-            const uint32_t e = t <= win.total ? win.nth(t) : ~0u;
-            const uint32_t nb = e - x + 1;  // varint bytes (huge: none in the window)
-            if (x > end || nb >= 10 || e >= end || nv + len > cap) {
-                // The checks in decoding order; a 10-byte varint is valid
-                // when its last byte is 0 or 1.
-                const int st = x > end                                        ? CODAG_E_TRUNCATED
-                               : nb > 10 || (nb == 10 && win.byte(e) > 1) ? CODAG_E_CORRUPT
-                               : e >= end                                     ? CODAG_E_TRUNCATED
-                               : nv + len > cap                               ? CODAG_E_OVERFLOW
-                                                                              : CODAG_OK;
-                if (st != CODAG_OK) {
-                    key = error_key(k, st);
+        if (W + kIdxStep < end) issue(t + 1);  // the other buffer: its window is done
+        __syncthreads();
+        // Terminator counts: thread tid takes region bytes [16 tid, 16 tid + 16).
+        uint32_t flags = 0;
+        if (tid < kIdxPieces) {
+            const uint4 v = reinterpret_cast<const uint4 *>(buf)[tid];
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const uint32_t tm = (~w[i] & 0x80808080u) >> 7;  // bits 0, 8, 16, 24
+                flags |= ((tm | (tm >> 7) | (tm >> 14) | (tm >> 21)) & 15) << (4 * i);
+            }
+        }
+        const uint32_t cnt = __builtin_popcount(flags);
+        const uint32_t incl = wave_inclusive_sum32(cnt);
+        if (l == kWave - 1) s_wsum[wave] = incl;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+#pragma unroll
+        for (uint32_t w = 0; w < kIdxWaves; w++) {
+            const uint32_t sw = s_wsum[w];
+            before += w < wave ? sw : 0;
+            total += sw;
+        }
+        if (tid < kIdxPieces) {
+            const uint32_t ex = before + incl - cnt;
+#pragma unroll
+            for (uint32_t b = 0; b < 16; b++) {
+                const uint32_t r = ex + __builtin_popcount(flags & ((1u << b) - 1));
+                s_tcount[16 * tid + b] = (uint16_t)r;
+                if ((flags >> b) & 1) s_tpos[r] = (uint16_t)(16 * tid + b);
+            }
+        }
+        __syncthreads();
+        // The group that would start at each position of the window.
+        for (uint32_t p = tid; p < kIdxStep; p += kWave * kIdxWaves) {
+            const uint32_t h = lds_byte(buf, p);
+            uint32_t ent;
+            if (h < 128) {
+                // Run: header, delta byte, base varint from r to terminator e.
+                const uint32_t r = p + 2, ti = s_tcount[r];
+                const uint32_t e = ti < total ? s_tpos[ti] : kIdxRegion;
+                const uint32_t nb = e - r + 1;
+                uint32_t code = kEntOk;
+                if (W + r > end) code = kEntTruncated;
+                else if (nb > 10 || (nb == 10 && lds_byte(buf, e) > 1)) code = kEntCorrupt;
+                else if (W + e >= end) code = kEntTruncated;
+                ent = make_ent(code == kEntOk ? e + 1 - p : 0, h + 3, code);
+            } else {
+                // Literal list of 256 - h varints: ends at its last terminator.
+                const uint32_t cntl = 256 - h, ti = s_tcount[p + 1] + cntl - 1;
+                const uint32_t e = ti < total ? s_tpos[ti] : kIdxRegion;
+                const bool open = e >= kIdxRegion || W + e >= end;
+                ent = make_ent(open ? 0 : e + 1 - p, cntl, open ? kEntOpen : kEntOk);
+            }
+            s_ent[p] = ent;
+        }
+        __syncthreads();
+        // The walk, by wave 0.
+        if (wave == 0) {
+            bool done = false;
+            while (true) {
+                if (nv >= cap) {
+                    done = true;
                     break;
                 }
+                if (pos >= end) {
+                    key = error_key(k, CODAG_E_TRUNCATED);
+                    done = true;
+                    break;
+                }
+                if (pos >= W + kIdxStep) break;  // on in the next window
+                const uint32_t e = uni(s_ent[pos - W]);
+                const uint32_t code = e >> 21, len = (e >> 13) & 0xff, off = e & 0x1fff;
+                if (code == kEntTruncated || code == kEntCorrupt) {
+                    key = error_key(k, code == kEntTruncated ? CODAG_E_TRUNCATED : CODAG_E_CORRUPT);
+                    done = true;
+                    break;
+                }
+                if (nv + len > cap) {
+                    key = error_key(k, CODAG_E_OVERFLOW);
+                    done = true;
+                    break;
+                }
+                const uint32_t gp = pos, gn = nv;
+                nv += len;
+                // Ranges that start at or before this group's first value start here.
+                while (j < kSplitWaves && gn >= next) {
+                    rg = l == j ? k : rg;
+                    rpos = l == j ? gp : rpos;
+                    rnv = l == j ? gn : rnv;
+                    j++;
+                    next = cap * j / kSplitWaves;  // cap < 2^28
+                }
+                k++;
+                if (code == kEntOpen) {
+                    // A list that does not end inside the chunk is still
+                    // recorded: its decode reports where it fails.
+                    open_end = true;
+                    done = true;
+                    break;
+                }
+                pos += off;
             }
-            pos = e + 1;
-            nv += len;
-        } else {
-            const uint32_t len = (uint32_t)(-h);
-            if (nv + len > cap) {
-                key = error_key(k, CODAG_E_OVERFLOW);
-                break;
-            }
-            // Skip `len` varints: the list ends at terminator number t
-            // counted from the window start.  A list that does not end
-            // inside the chunk is still recorded: its decode reports where
-            // it fails.
-            uint32_t t = win.before(pos + 1) + len;
-            while (t > win.total && win.w + 512 < end) {
-                t -= win.total;
-                win.load(in, win.w + 512);
-            }
-            if (t > win.total) {
-                open_end = true;
-            } else {
-                const uint32_t e = win.nth(t);
-                open_end = e >= end;
-                pos = e + 1;
-            }
-            nv += len;
+            if (l == 0) s_done = done ? 1u : 0u;
         }
-        // Ranges that start at or before this group's first value start here.
-        while (j < kSplitWaves && gn >= next) {
-            rg = l == j ? k : rg;
-            rpos = l == j ? gp : rpos;
-            rnv = l == j ? gn : rnv;
-            j++;
-            next = cap * j / kSplitWaves;  // cap < 2^28
-        }
-        k++;
-        if (open_end) break;
+        __syncthreads();
+        if (s_done) break;
+    }
+    if (wave != 0) {
+        wait_vm();  // a load issued one window ahead may still be landing
+        return;
     }
     if (!open_end && key == ~0ull && pos != end) key = error_key(k, CODAG_E_CORRUPT);
     // Ranges not started are empty; each ends where the next one starts.
     rg = l >= j ? k : rg;
     const uint32_t rend = __shfl_down(rg, 1, kWave);
     if (l < kSplitWaves) range[(size_t)c * kSplitWaves + l] = make_uint4(rg, rend, rpos, rnv);
-    keys[2 * c] = key;
+    if (l == 0) keys[2 * c] = key;
     __builtin_amdgcn_s_waitcnt(0);
 }
 
@@ -214,8 +279,10 @@ __global__ void __launch_bounds__(kWave * kSplitWpb)
     __builtin_amdgcn_s_waitcnt(0);
 }
 
-// Per chunk, the earlier of the two passes' errors.
-__global__ void rle_v1_finish(uint32_t n, const unsigned long long *keys, int32_t *status,
+// Per chunk, the earlier of the two passes' errors (both passes key errors
+// the same way: RLE v1 by group index, RLE v2 by the failing run's first
+// value).
+__global__ void split_finish(uint32_t n, const unsigned long long *keys, int32_t *status,
                               unsigned long long *err) {
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
@@ -242,12 +309,281 @@ int launch_rle_v1_split(const uint8_t *comp, const uint64_t *coff, uint8_t *out,
     uint4 *range = static_cast<uint4 *>(ws);
     unsigned long long *keys =
         reinterpret_cast<unsigned long long *>(static_cast<char *>(ws) + range_bytes);
-    hipLaunchKernelGGL(rle_v1_index, dim3(n), dim3(kWave), 0, s, comp, coff, out, ooff, n, range,
-                       keys);
+    hipLaunchKernelGGL(rle_v1_index, dim3(n), dim3(kWave * kIdxWaves), 0, s, comp, coff, out, ooff, n,
+                       range, keys);
     const uint32_t gb = (n * kSplitWaves + kSplitWpb - 1) / kSplitWpb;
     hipLaunchKernelGGL(rle_v1_groups, dim3(gb), dim3(kWave * kSplitWpb), 0, s, comp, coff, out,
                        ooff, n, range, keys);
-    hipLaunchKernelGGL(rle_v1_finish, dim3((n + 255) / 256), dim3(256), 0, s, n, keys, status, err);
+    hipLaunchKernelGGL(split_finish, dim3((n + 255) / 256), dim3(256), 0, s, n, keys, status, err);
+    hipError_t e = hipGetLastError();
+    if (!workspace && hipFreeAsync(ws, s) != hipSuccess) return CODAG_E_HIP;
+    return e == hipSuccess ? CODAG_OK : CODAG_E_HIP;
+}
+
+// ---- RLE v2 ------------------------------------------------------------
+//
+// The same two passes for RLE v2.  A run's header gives its byte length
+// (DELTA after two varints), so the index pass parses headers only: long
+// runs are stepped over, and SHORT_REPEAT stretches are walked 64 bytes at
+// a time with every lane parsing the header at its own byte (the decoder's
+// chain walk without the values and stores).  It cuts the runs into
+// kV2Ranges ranges of about equal output at run boundaries; each range is
+// then decoded by one wave of the plain decoder, started at the range's
+// first run and stopped at its last value.  Errors are keyed by the first
+// value of the failing run (every run has at least one value, so that order
+// is the stream order): the index pass reports structural errors (and
+// leftover input, keyed at the end), the decoding waves the rest.
+
+constexpr uint32_t kV2Ranges = 8;  // decoding waves per chunk
+constexpr int kV2IndexWpb = 4;     // index pass: waves per block
+constexpr int kV2DecodeWpb = 4;    // decode pass: waves per block
+using V2IndexRing = InRingT<4096>;
+
+// Where each range starts (byte position, first value) and the value at
+// which the index pass stopped (the chunk's value count, or the first value
+// of the run where it found an error).
+struct V2Split {
+    uint2 start[kV2Ranges];
+    uint32_t stop, pad[3];
+};
+static_assert(sizeof(V2Split) + 2 * sizeof(unsigned long long) == kSplitV2WorkspacePerChunk,
+              "workspace layout");
+
+__device__ __forceinline__ uint32_t v2_threshold(uint32_t cap, uint32_t j) {
+    return (uint32_t)((uint64_t)cap * j / kV2Ranges);
+}
+
+// Ranges whose first value is at most nv start at the run at (pos, nv).
+__device__ __forceinline__ void v2_cut(uint32_t &j, uint32_t cap, uint32_t pos, uint32_t nv,
+                                       V2Split *sp) {
+    while (j < kV2Ranges && nv >= v2_threshold(cap, j)) {
+        if (lane() == 0) sp->start[j] = make_uint2(pos, nv);
+        j++;
+    }
+}
+
+// A stretch of SHORT_REPEAT runs from pos, as the decoder walks it: lane l
+// parses the header at pos + l, the chain of runs is followed from lane 0
+// with one lane read per run, and a wave prefix sum gives each run's first
+// value (for the cuts).  Stops like the decoder: at the first header that is
+// not a SHORT_REPEAT, at the end of input, or with the output full.  On an
+// error, errnv is the first value of the failing run.
+template <class Ring>
+__device__ __forceinline__ int v2_index_short_repeats(Ring &in, uint32_t &pos, uint32_t end,
+                                                      uint32_t &nv, uint32_t cap, uint32_t &j,
+                                                      V2Split *sp, uint32_t &errnv) {
+    const uint32_t l = lane();
+    for (;;) {
+        in.ensure(pos + 72);
+        const uint32_t at_b = pos + l;
+        const uint32_t h = (in.word(at_b >> 2) >> (8 * (at_b & 3))) & 0xff;
+        const uint32_t w = ((h >> 3) & 7) + 1, cs = (h & 7) + 3;
+        const uint32_t nxt = (h >> 6) == 0 && at_b + 1 + w <= end ? l + 1 + w : 128 + l;
+        uint32_t s = 0;
+        uint64_t starts = 0;
+        do {
+            starts |= 1ull << s;
+            s = readlane(nxt, s);
+        } while (s < kWave);
+        if (s >= 128) {
+            s -= 128;
+            starts &= ~(1ull << s);
+        }
+        const bool mine = (starts >> l) & 1;
+        const uint32_t c = mine ? cs : 0;
+        const uint32_t at = nv + wave_inclusive_sum32(c) - c;
+        const uint32_t n1 = uni(readlane(at + c, kWave - 1));
+        uint32_t ff = kWave, fo = kWave;
+        if (n1 > cap) {
+            const uint64_t full = ballot(mine && at >= cap), over = ballot(mine && at < cap && at + c > cap);
+            ff = full ? (uint32_t)__builtin_ctzll(full) : kWave;
+            fo = over ? (uint32_t)__builtin_ctzll(over) : kWave;
+        }
+        const uint32_t lim = min(ff, fo);
+        while (j < kV2Ranges && v2_threshold(cap, j) < n1) {
+            const uint64_t m = ballot(mine && l < lim && at >= v2_threshold(cap, j));
+            if (!m) break;
+            const uint32_t L = (uint32_t)__builtin_ctzll(m);
+            const uint32_t a = uni(readlane(at, L));
+            if (l == 0) sp->start[j] = make_uint2(pos + L, a);
+            j++;
+        }
+        if (fo < ff) {
+            errnv = uni(readlane(at, fo));
+            return CODAG_E_OVERFLOW;
+        }
+        if (ff < kWave) {
+            nv = cap;
+            pos += ff;
+            return CODAG_OK;
+        }
+        nv = n1;
+        if (s < kWave) {
+            int st = CODAG_OK;
+            if (pos + s < end && nv < cap) {
+                const uint32_t hs = readlane(h, s);
+                if ((hs >> 6) == 0) {
+                    st = nv + (hs & 7) + 3 > cap ? CODAG_E_OVERFLOW : CODAG_E_TRUNCATED;
+                    errnv = nv;
+                }
+            }
+            pos += s;
+            return st;
+        }
+        pos += s;
+        if (nv >= cap || pos >= end) return CODAG_OK;
+    }
+}
+
+// Index pass, one wave per chunk: the checks of the decoder's header parse,
+// in its order.
+__global__ void __launch_bounds__(kWave * kV2IndexWpb)
+    rle_v2_index(const uint8_t *comp, const uint64_t *coff, uint8_t *out, const uint64_t *ooff,
+                 uint32_t n, V2Split *split, unsigned long long *keys) {
+    __shared__ __align__(16) uint32_t s_ring[kV2IndexWpb][V2IndexRing::kLdsWords];
+    __shared__ __align__(16) uint32_t s_land[kV2IndexWpb][V2IndexRing::kLand];
+    const uint32_t wave = uni(threadIdx.x / kWave);
+    const uint32_t c = blockIdx.x * kV2IndexWpb + wave;
+    if (c >= n) return;
+    V2Split *sp = &split[c];
+    if (lane() == 0) keys[2 * c + 1] = ~0ull;  // the decode pass's key
+    const uint64_t i0 = coff[c], i1 = coff[c + 1], o0 = ooff[c], o1 = ooff[c + 1];
+    const uint32_t in_len = (uint32_t)(i1 - i0), out_len = (uint32_t)(o1 - o0);
+    if ((((i1 - i0) | (o1 - o0)) >> 31) != 0 || (out_len & 7) ||
+        (reinterpret_cast<uintptr_t>(out + o0) & 7)) {
+        if (lane() < kV2Ranges) sp->start[lane()] = make_uint2(0, 0);
+        if (lane() == 0) {
+            sp->stop = 0;
+            keys[2 * c] = error_key(0, CODAG_E_INVALID_ARGUMENT);
+        }
+        return;
+    }
+    V2IndexRing in;
+    in.init(comp + i0, in_len, s_ring[wave], s_land[wave]);
+    const uint32_t end = in.gend, cap = out_len / 8;
+    uint32_t pos = in.skip, nv = 0, j = 0, errnv = 0;
+    int st = CODAG_OK;
+    while (nv < cap) {
+        if (pos >= end) {
+            st = CODAG_E_TRUNCATED;
+            errnv = nv;
+            break;
+        }
+        in.ensure(pos + 24);
+        const uint64_t x = in.peek8(pos);
+        const uint32_t b0 = (uint32_t)(x & 0xff), type = b0 >> 6;
+        if (type == 0) {
+            st = v2_index_short_repeats(in, pos, end, nv, cap, j, sp, errnv);
+            if (st) break;
+            continue;
+        }
+        v2_cut(j, cap, pos, nv, sp);
+        errnv = nv;
+        if (pos + 2 > end) {
+            st = CODAG_E_TRUNCATED;
+            break;
+        }
+        const uint32_t b1 = (uint32_t)((x >> 8) & 0xff);
+        const uint32_t len = (((b0 & 1) << 8) | b1) + 1;
+        if (type == 1) {
+            const uint32_t w = orc_width((b0 >> 1) & 31);
+            if (nv + len > cap) { st = CODAG_E_OVERFLOW; break; }
+            const uint32_t nbytes = (len * w + 7) >> 3;
+            if (pos + 2 + nbytes > end) { st = CODAG_E_TRUNCATED; break; }
+            pos += 2 + nbytes;
+        } else if (type == 2) {
+            if (pos + 4 > end) { st = CODAG_E_TRUNCATED; break; }
+            const uint32_t b2 = (uint32_t)((x >> 16) & 0xff), b3 = (uint32_t)((x >> 24) & 0xff);
+            const uint32_t w = orc_width((b0 >> 1) & 31);
+            const uint32_t bw = (b2 >> 5) + 1, pw = orc_width(b2 & 31);
+            const uint32_t pgw = (b3 >> 5) + 1, pll = b3 & 31;
+            const uint32_t ew = orc_fit_width(pgw + pw);
+            if (ew == 0) { st = CODAG_E_CORRUPT; break; }
+            if (nv + len > cap) { st = CODAG_E_OVERFLOW; break; }
+            const uint32_t bsec = pos + 4;
+            if (bsec + bw > end) { st = CODAG_E_TRUNCATED; break; }
+            const uint32_t dsec = bsec + bw, dbytes = (len * w + 7) >> 3;
+            if (dsec + dbytes > end) { st = CODAG_E_TRUNCATED; break; }
+            const uint32_t psec = dsec + dbytes, pbytes = (pll * ew + 7) >> 3;
+            if (psec + pbytes > end) { st = CODAG_E_TRUNCATED; break; }
+            pos = psec + pbytes;
+        } else {
+            const uint32_t code = (b0 >> 1) & 31;
+            const uint32_t w = code ? orc_width(code) : 0;
+            uint32_t p = pos + 2;
+            uint64_t z;
+            st = read_varint(in, p, end, z);
+            if (st) break;
+            st = read_varint(in, p, end, z);
+            if (st) break;
+            if (nv + len > cap) { st = CODAG_E_OVERFLOW; break; }
+            if (w) {
+                const uint32_t nd = len >= 2 ? len - 2 : 0, nbytes = (nd * w + 7) >> 3;
+                if (p + nbytes > end) { st = CODAG_E_TRUNCATED; break; }
+                p += nbytes;
+            }
+            pos = p;
+        }
+        nv += len;
+    }
+    if (st == CODAG_OK && pos != end) {
+        st = CODAG_E_CORRUPT;  // input left over once the output is full
+        errnv = nv;
+    }
+    const uint32_t stop = st == CODAG_OK ? nv : errnv;
+    // Ranges not started are empty.
+    for (uint32_t k = j; k < kV2Ranges; k++)
+        if (lane() == 0) sp->start[k] = make_uint2(pos, stop);
+    if (lane() == 0) {
+        sp->stop = stop;
+        keys[2 * c] = st == CODAG_OK ? ~0ull : error_key(errnv, st);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+}
+
+// Decode pass: wave j of chunk c decodes range j with the plain decoder,
+// from its first run to the next range's first value.
+__global__ void __launch_bounds__(kWave * kV2DecodeWpb)
+    rle_v2_ranges(const uint8_t *comp, const uint64_t *coff, uint8_t *out, const uint64_t *ooff,
+                  uint32_t n, const V2Split *split, unsigned long long *keys) {
+    __shared__ __align__(16) uint32_t s_ring[kV2DecodeWpb][kRingLdsWords];
+    __shared__ __align__(16) uint32_t s_land[kV2DecodeWpb][kLandWords];
+    const uint32_t wave = uni(threadIdx.x / kWave);
+    const uint32_t gid = blockIdx.x * kV2DecodeWpb + wave;
+    const uint32_t c = gid / kV2Ranges, j = gid % kV2Ranges;
+    if (c >= n) return;
+    const V2Split *sp = &split[c];
+    const uint2 r = sp->start[j];
+    const uint32_t e = uni(j + 1 < kV2Ranges ? sp->start[j + 1].y : sp->stop);
+    uint32_t pos = uni(r.x), nv = uni(r.y);
+    if (nv >= e) return;
+    const uint64_t i0 = coff[c], i1 = coff[c + 1], o0 = ooff[c];
+    InRing in;
+    in.init_at(comp + i0, (uint32_t)(i1 - i0), s_ring[wave], s_land[wave], pos);
+    uint64_t *dst = reinterpret_cast<uint64_t *>(out + o0);
+    const int st = decode_rle_v2_runs(in, pos, in.gend, dst, nv, e);
+    if (st != CODAG_OK && lane() == 0) atomicMin(&keys[2 * c + 1], (unsigned long long)error_key(nv, st));
+    __builtin_amdgcn_s_waitcnt(0);
+}
+
+size_t rle_v2_split_workspace(uint32_t n) {
+    return (size_t)n * kSplitV2WorkspacePerChunk;
+}
+
+int launch_rle_v2_split(const uint8_t *comp, const uint64_t *coff, uint8_t *out,
+                        const uint64_t *ooff, uint32_t n, int32_t *status, unsigned long long *err,
+                        hipStream_t s, void *workspace) {
+    void *ws = workspace;
+    if (!ws && hipMallocAsync(&ws, rle_v2_split_workspace(n), s) != hipSuccess) return CODAG_E_HIP;
+    V2Split *split = static_cast<V2Split *>(ws);
+    unsigned long long *keys =
+        reinterpret_cast<unsigned long long *>(static_cast<char *>(ws) + (size_t)n * sizeof(V2Split));
+    hipLaunchKernelGGL(rle_v2_index, dim3((n + kV2IndexWpb - 1) / kV2IndexWpb),
+                       dim3(kWave * kV2IndexWpb), 0, s, comp, coff, out, ooff, n, split, keys);
+    const uint32_t gb = (uint32_t)(((uint64_t)n * kV2Ranges + kV2DecodeWpb - 1) / kV2DecodeWpb);
+    hipLaunchKernelGGL(rle_v2_ranges, dim3(gb), dim3(kWave * kV2DecodeWpb), 0, s, comp, coff, out,
+                       ooff, n, split, keys);
+    hipLaunchKernelGGL(split_finish, dim3((n + 255) / 256), dim3(256), 0, s, n, keys, status, err);
     hipError_t e = hipGetLastError();
     if (!workspace && hipFreeAsync(ws, s) != hipSuccess) return CODAG_E_HIP;
     return e == hipSuccess ? CODAG_OK : CODAG_E_HIP;

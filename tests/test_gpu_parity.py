@@ -55,10 +55,19 @@ def test_rle_v1_small(dev, wpb):
 
 
 @pytest.mark.parametrize("wpb", [1, 2, 4])
-def test_rle_v2_small(dev, wpb):
+def test_rle_v2_small_one_wave(dev, wpb):
     ch = workloads.rle_v2_workload(seed=5, n_values=300_001, chunk_values=32768)
-    _say(f"rle_v2 small wpb={wpb} chunks={ch.n_chunks}")
-    assert (assert_parity(oracle.RLE_V2, ch, dev, waves_per_block=wpb) == 0).all()
+    _say(f"rle_v2 small one wave per chunk wpb={wpb} chunks={ch.n_chunks}")
+    assert (assert_parity(oracle.RLE_V2, ch, dev, waves_per_block=wpb, group_parallel=1) == 0).all()
+
+
+@pytest.mark.parametrize("chunk_values", [32768, 5000, 700])
+def test_rle_v2_small_group_parallel(dev, chunk_values):
+    """Chunks long and short enough that the ranges hold many runs, a few, or
+    none (more ranges than runs)."""
+    ch = workloads.rle_v2_workload(seed=5, n_values=300_001, chunk_values=chunk_values)
+    _say(f"rle_v2 small group-parallel chunk_values={chunk_values} chunks={ch.n_chunks}")
+    assert (assert_parity(oracle.RLE_V2, ch, dev, group_parallel=2) == 0).all()
 
 
 @pytest.mark.parametrize("tb", [9, 10])
@@ -98,8 +107,9 @@ def test_rle_v2_each_subencoding(dev):
             blobs.append(enc.encode_rle_v2(v, np.array([n]), np.array([kind], dtype=np.uint8)))
             sizes.append(8 * n)
     ch = _chunks(oracle.RLE_V2, blobs, sizes)
-    _say(f"rle_v2 forced sub-encodings chunks={ch.n_chunks}")
-    assert (assert_parity(oracle.RLE_V2, ch, dev) == 0).all()
+    for gp in (1, 2):
+        _say(f"rle_v2 forced sub-encodings chunks={ch.n_chunks} group_parallel={gp}")
+        assert (assert_parity(oracle.RLE_V2, ch, dev, group_parallel=gp) == 0).all()
 
 
 def test_rle_extremes(dev):
@@ -113,7 +123,7 @@ def test_rle_extremes(dev):
             np.column_stack([np.repeat(np.random.default_rng(4).integers(-9999, 9999, 2000), 3).reshape(-1, 3),
                              np.random.default_rng(5).integers(I64_MIN, I64_MAX, 2000)]).reshape(-1)]
     for codec, encode, gp in ((oracle.RLE_V1, enc.encode_rle_v1, 1), (oracle.RLE_V1, enc.encode_rle_v1, 2),
-                              (oracle.RLE_V2, enc.encode_rle_v2, 0)):
+                              (oracle.RLE_V2, enc.encode_rle_v2, 1), (oracle.RLE_V2, enc.encode_rle_v2, 2)):
         ch = _chunks(codec, [encode(v) for v in vals], [8 * v.size for v in vals])
         _say(f"rle extremes codec={codec} group_parallel={gp}")
         assert (assert_parity(codec, ch, dev, group_parallel=gp) == 0).all()
@@ -192,7 +202,7 @@ def test_capacity_statuses(dev):
     vals = np.arange(200, dtype=np.int64) * 7
     blobs, sizes = [], []
     for codec, encode, gp in ((oracle.RLE_V1, enc.encode_rle_v1, 1), (oracle.RLE_V1, enc.encode_rle_v1, 2),
-                              (oracle.RLE_V2, enc.encode_rle_v2, 0)):
+                              (oracle.RLE_V2, enc.encode_rle_v2, 1), (oracle.RLE_V2, enc.encode_rle_v2, 2)):
         data = encode(vals)
         ch = _chunks(codec, [data, data, data, data + b"\x00", data[:-1]], [1600, 1592, 1608, 1600, 1600])
         st = assert_parity(codec, ch, dev, group_parallel=gp)
@@ -217,8 +227,9 @@ def test_short_repeat_stretch_ending_at_capacity(dev):
             blobs.append(runs + tail)
             sizes.append(8 * cap)
     ch = _chunks(oracle.RLE_V2, blobs, sizes)
-    st = assert_parity(oracle.RLE_V2, ch, dev)
-    assert st[0] == oracle.E_CORRUPT and st[1] == oracle.E_OVERFLOW
+    for gp in (1, 2):
+        st = assert_parity(oracle.RLE_V2, ch, dev, group_parallel=gp)
+        assert st[0] == oracle.E_CORRUPT and st[1] == oracle.E_OVERFLOW
 
 
 # ---- corrupt inputs: same status class as the oracle -------------------------
@@ -238,8 +249,8 @@ def _mutants(blobs, rng, count):
     return out
 
 
-@pytest.mark.parametrize("codec,gp", [(oracle.RLE_V1, 1), (oracle.RLE_V1, 2), (oracle.RLE_V2, 0),
-                                      (oracle.DEFLATE, 0)])
+@pytest.mark.parametrize("codec,gp", [(oracle.RLE_V1, 1), (oracle.RLE_V1, 2), (oracle.RLE_V2, 1),
+                                      (oracle.RLE_V2, 2), (oracle.DEFLATE, 0)])
 def test_corrupt_streams_status_parity(dev, codec, gp):
     rng = np.random.default_rng(100 + codec)
     if codec == oracle.DEFLATE:
@@ -270,10 +281,11 @@ def test_full_rle_v1(dev, gp):
     assert (assert_parity(oracle.RLE_V1, ch, dev, group_parallel=gp) == 0).all()
 
 
-def test_full_rle_v2(dev):
+@pytest.mark.parametrize("gp", [0, 1])
+def test_full_rle_v2(dev, gp):
     ch = workloads.rle_v2_workload(seed=0)
-    _say(f"full rle_v2 chunks={ch.n_chunks}")
-    assert (assert_parity(oracle.RLE_V2, ch, dev, threads=16) == 0).all()
+    _say(f"full rle_v2 chunks={ch.n_chunks} group_parallel={gp}")
+    assert (assert_parity(oracle.RLE_V2, ch, dev, threads=16, group_parallel=gp) == 0).all()
 
 
 def test_full_deflate(dev):

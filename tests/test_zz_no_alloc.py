@@ -64,6 +64,10 @@ CASES = [
      lambda: workloads.rle_v2_workload(seed=6, n_values=400_000, chunk_values=32768),
      lambda: workloads.rle_v2_workload(seed=7, n_values=50_000, chunk_values=32768),
      {}),
+    (oracle.RLE_V2,
+     lambda: workloads.rle_v2_workload(seed=12, n_values=2048 * 300, chunk_values=300),  # 2048 chunks
+     lambda: _mutated(workloads.rle_v2_workload(seed=13, n_values=90_000, chunk_values=3000), 2, 6),
+     {"group_parallel": 2}),
     (oracle.DEFLATE,
      lambda: workloads.deflate_workload(seed=8, total_bytes=40 * 65536),
      lambda: workloads.deflate_workload(seed=9, total_bytes=5 * 65536 + 1000),
@@ -85,17 +89,27 @@ def test_noalloc_matches_ex(dev, case):
         codag.get_error()
 
 
-def test_noalloc_rejects_workspace_beyond_scratch(dev):
+@pytest.mark.parametrize("codec,over", [(oracle.RLE_V1, 723), (oracle.RLE_V2, 2049)])
+def test_noalloc_rejects_workspace_beyond_scratch(dev, codec, over):
+    """Forced group-parallel launches whose workspace exceeds the scratch
+    array (RLE v1: 272 bytes per chunk, RLE v2: 96, of 196,608) are refused;
+    the allocating entry point takes them, and with the default path choice
+    the no-allocation entry point decodes them one wave per chunk."""
     import paper_2307_03760_amd as codag
-    ch = workloads.rle_v1_workload(seed=10, n_values=257 * 100, chunk_values=100)
-    assert ch.n_chunks == 257
+    make = workloads.rle_v1_workload if codec == oracle.RLE_V1 else workloads.rle_v2_workload
+    ch = make(seed=10, n_values=over * 64, chunk_values=64)
+    assert ch.n_chunks == over
+    _say(f"noalloc limit codec {codec}: {over} chunks")
     with pytest.raises(codag.CodagError) as e:
-        _decode(codag.decompress_noalloc, oracle.RLE_V1, ch, dev, group_parallel=2)
+        _decode(codag.decompress_noalloc, codec, ch, dev, group_parallel=2)
     assert e.value.status == codag.E_INVALID_ARGUMENT
-    # The allocating entry point takes the same launch.
-    _, st = _decode(codag.decompress, oracle.RLE_V1, ch, dev, group_parallel=2)
+    _, st = _decode(codag.decompress, codec, ch, dev, group_parallel=2)
     assert (st == 0).all()
-    # With the default path choice 257 chunks go one wave per chunk: no workspace.
-    ref, ref_st = _decode(codag.decompress, oracle.RLE_V1, ch, dev)
-    got, got_st = _decode(codag.decompress_noalloc, oracle.RLE_V1, ch, dev)
+    ref, ref_st = _decode(codag.decompress, codec, ch, dev)
+    got, got_st = _decode(codag.decompress_noalloc, codec, ch, dev)
     assert np.array_equal(got_st, ref_st) and np.array_equal(got, ref)
+    # One below the limit fits.
+    sub = make(seed=11, n_values=(over - 1) * 64, chunk_values=64)
+    ref, ref_st = _decode(codag.decompress, codec, sub, dev, group_parallel=2)
+    got, got_st = _decode(codag.decompress_noalloc, codec, sub, dev, group_parallel=2)
+    assert np.array_equal(got_st, ref_st) and np.array_equal(got, ref) and (got_st == 0).all()
