@@ -279,10 +279,14 @@ __device__ __forceinline__ int rle_v2_short_repeats(InRing &in, uint32_t &pos, u
         const uint32_t nxt = (h >> 6) == 0 && pos + l + 1 + w <= end ? l + 1 + w : 128 + l;
         uint32_t s = 0;
         uint64_t starts = 0;
-        do {
+        for (;;) {  // two runs per loop trip: one taken branch per two runs
             starts |= 1ull << s;
             s = readlane(nxt, s);
-        } while (s < kWave);
+            if (s >= kWave) break;
+            starts |= 1ull << s;
+            s = readlane(nxt, s);
+            if (s >= kWave) break;
+        }
         if (s >= 128) {
             s -= 128;
             starts &= ~(1ull << s);

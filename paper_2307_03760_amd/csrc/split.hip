@@ -26,21 +26,26 @@ constexpr int kSplitWpb = 4;          // decode pass: waves per block
 // a few KiB), more than the one-wave decoder's 1 KiB.
 using GroupRing = InRingT<4096>;
 
-// Index pass, one workgroup of kIdxWaves waves per chunk.  The chunk is
-// taken in windows of kIdxStep byte positions on a fixed grid.  For every
-// position p of a window the workgroup works out, in parallel, the group
-// that would start at p -- its length in bytes and in values, and what its
-// header and run base say about errors (runs), or where its last varint ends
-// (literal lists) -- from a count of varint terminator bytes (bit 7 clear)
-// over the window and a lookahead long enough for any valid group.  Then one
-// wave walks the real groups from where the previous window's walk left off,
-// one LDS read per group, and cuts them into kSplitWaves ranges of about
-// equal output.  Each window's bytes arrive by direct-to-LDS loads issued one
-// window ahead.
-constexpr uint32_t kIdxWaves = 8;
+// Index pass, one workgroup per chunk: one walker wave and kIdxHelpers
+// helper waves.  The chunk is taken in windows of kIdxStep byte positions
+// on a fixed grid.  For every position p of a window the helpers work out,
+// in parallel, the group that would start at p -- its length in bytes and
+// in values, and what its header and run base say about errors (runs), or
+// where its last varint ends (literal lists) -- from a count of varint
+// terminator bytes (bit 7 clear) over the window and a lookahead long
+// enough for any valid group.  The walker follows the real groups through
+// those entries, one LDS read per group, and cuts them into kSplitWaves
+// ranges of about equal output.  The helpers prepare window t + 1 while the
+// walker walks window t (the two sides meet through LDS counters, not
+// workgroup barriers, so neither waits for the other's whole step), and
+// each window's bytes arrive by direct-to-LDS loads issued one window
+// ahead.
+constexpr uint32_t kIdxHelpers = 15;
+constexpr uint32_t kIdxThreads = kWave * (kIdxHelpers + 1);
 constexpr uint32_t kIdxStep = 4096;                    // positions per window
 constexpr uint32_t kIdxAhead = 1536;                   // a valid group spans at most 1 + 10 * 128 bytes
 constexpr uint32_t kIdxRegion = kIdxStep + kIdxAhead;  // bytes read per window
+constexpr uint32_t kIdxWords = kIdxRegion / 4;
 constexpr uint32_t kIdxPieces = kIdxRegion / 16;       // 16-byte loads per window
 static_assert(kIdxRegion % 16 == 0 && kIdxStep >= kIdxAhead, "window shape");
 
@@ -52,8 +57,29 @@ __device__ __forceinline__ uint32_t make_ent(uint32_t off, uint32_t len, uint32_
     return off | (len << 13) | (code << 21);
 }
 
-__device__ __forceinline__ uint32_t lds_byte(const uint32_t *buf, uint32_t x) {
-    return (buf[x >> 2] >> (8 * (x & 3))) & 0xff;
+// One bit per terminator byte (bit 7 clear) of a little-endian word.
+__device__ __forceinline__ uint32_t term_bits(uint32_t w) {
+    const uint32_t t = (~w & 0x80808080u) >> 7;  // bits 0, 8, 16, 24
+    return (t | (t >> 7) | (t >> 14) | (t >> 21)) & 15;
+}
+
+// Counters the walker and the helpers meet at (LDS, monotone).
+__device__ __forceinline__ uint32_t lds_load_acquire(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_store_release(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void wait_at_least(const uint32_t *p, uint32_t v) {
+    while (lds_load_acquire(p) < v) __builtin_amdgcn_s_sleep(1);
+}
+// A barrier of the helper waves alone: the counter only grows, each
+// crossing adds one per helper wave.
+__device__ __forceinline__ void helper_barrier(uint32_t *ctr, uint32_t &gen) {
+    gen++;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (lane() == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    wait_at_least(ctr, gen * kIdxHelpers);
 }
 
 // Index pass.  The groups are cut into kSplitWaves ranges of about equal
@@ -61,15 +87,16 @@ __device__ __forceinline__ uint32_t lds_byte(const uint32_t *buf, uint32_t x) {
 // position and first value of the first group).  keys[2c] = the first
 // structural error (group << 4 | -status), or all ones; groups from that
 // one on are in no range.
-__global__ void __launch_bounds__(kWave * kIdxWaves)
+__global__ void __launch_bounds__(kIdxThreads)
     rle_v1_index(const uint8_t *comp, const uint64_t *coff, uint8_t *out, const uint64_t *ooff,
                  uint32_t n, uint4 *range, unsigned long long *keys) {
-    __shared__ __align__(16) uint32_t s_buf[2][kIdxRegion / 4];
-    __shared__ uint16_t s_tcount[kIdxRegion];  // terminators before each region byte
-    __shared__ uint16_t s_tpos[kIdxRegion];    // region position of each terminator
-    __shared__ uint32_t s_ent[kIdxStep];
-    __shared__ uint32_t s_wsum[kIdxWaves];
-    __shared__ uint32_t s_done;
+    __shared__ __align__(16) uint32_t s_buf[2][kIdxWords];
+    __shared__ __align__(16) uint32_t s_before[kIdxWords];  // terminators before each word
+    __shared__ uint16_t s_tpos[kIdxRegion];                 // region position of each terminator
+    __shared__ __align__(16) uint32_t s_ent[2][kIdxStep];
+    __shared__ uint32_t s_wsum[kIdxHelpers];
+    __shared__ uint32_t s_sync[4];  // helper barrier, windows ready, windows walked, walk done
+    __shared__ uint32_t s_stop;     // the walk-done flag as the helpers see it this window
     const uint32_t tid = threadIdx.x, wave = uni(tid / kWave), l = lane();
     const uint32_t c = blockIdx.x;
     if (c >= n) return;
@@ -86,158 +113,195 @@ __global__ void __launch_bounds__(kWave * kIdxWaves)
     const uint32_t skip = (uint32_t)(reinterpret_cast<uintptr_t>(chunk) & 15);
     const uint8_t *gbase = chunk - skip;  // positions are relative to the 16-byte hull
     const uint32_t end = skip + in_len, cap = out_len / 8;
+    if (tid < 4) s_sync[tid] = 0;
+    __syncthreads();
 
-    // Region of window t: bytes [t * kIdxStep, t * kIdxStep + kIdxRegion),
-    // one 1 KiB block of 16-byte loads per wave instruction.
-    auto issue = [&](uint32_t t) {
-        const uint32_t W = t * kIdxStep;
-        for (uint32_t b = wave; b * kWave < kIdxPieces; b += kIdxWaves) {
-            const uint32_t q = b * kWave + l, at = W + 16 * q;
-            if (q < kIdxPieces && at < end)
-                __builtin_amdgcn_global_load_lds(gbase + at, (lds_void *)(&s_buf[t & 1][b * 256]), 16, 0, 0);
+    if (wave != 0) {
+        // ---- helpers: prepare each window's entries, one window ahead of
+        // the walker.
+        const uint32_t h = wave - 1, ht = tid - kWave;  // helper index, helper thread index
+        uint32_t gen = 0;
+        // Region of window t into buffer t & 1: 1 KiB blocks of 16-byte
+        // loads, one per helper wave instruction.
+        auto issue = [&](uint32_t t) {
+            const uint32_t W = t * kIdxStep;
+            for (uint32_t b = h; b * kWave < kIdxPieces; b += kIdxHelpers) {
+                const uint32_t q = b * kWave + l, at = W + 16 * q;
+                if (q < kIdxPieces && at < end)
+                    __builtin_amdgcn_global_load_lds(gbase + at, (lds_void *)(&s_buf[t & 1][b * 256]), 16, 0, 0);
+            }
+        };
+        issue(0);
+        for (uint32_t t = 0; t * kIdxStep < end; t++) {
+            const uint32_t W = t * kIdxStep;
+            uint32_t *buf = s_buf[t & 1];
+            wait_vm();
+            // One helper samples the walker's flag before the barrier, so
+            // every helper takes the same decision after it.
+            if (h == 0 && l == 0) s_stop = lds_load_acquire(&s_sync[3]);
+            helper_barrier(&s_sync[0], gen);  // the region has landed
+            if (s_stop) break;
+            // Bytes past the end of the chunk read as zero (terminators).
+            for (uint32_t q = ht; q < kIdxPieces; q += kWave * kIdxHelpers) {
+                const uint32_t at = W + 16 * q;
+                if (at + 16 > end) {
+                    uint4 v = reinterpret_cast<uint4 *>(buf)[q];
+                    const uint32_t valid = at < end ? end - at : 0;
+                    uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int i = 0; i < 4; i++) {
+                        const int keep = (int)valid - 4 * i;
+                        w[i] &= keep >= 4 ? 0xffffffffu : keep <= 0 ? 0u : ((1u << (8 * keep)) - 1);
+                    }
+                    reinterpret_cast<uint4 *>(buf)[q] = make_uint4(w[0], w[1], w[2], w[3]);
+                }
+            }
+            // The other buffer held window t - 1, whose entries are done.
+            if (W + kIdxStep < end) issue(t + 1);
+            helper_barrier(&s_sync[0], gen);
+            // Terminator counts: helper thread ht takes region bytes
+            // [16 ht, 16 ht + 16).
+            uint32_t tb[4] = {0, 0, 0, 0};
+            if (ht < kIdxPieces) {
+                const uint4 v = reinterpret_cast<const uint4 *>(buf)[ht];
+                tb[0] = term_bits(v.x);
+                tb[1] = term_bits(v.y);
+                tb[2] = term_bits(v.z);
+                tb[3] = term_bits(v.w);
+            }
+            const uint32_t c0 = __builtin_popcount(tb[0]), c1 = __builtin_popcount(tb[1]);
+            const uint32_t c2 = __builtin_popcount(tb[2]), c3 = __builtin_popcount(tb[3]);
+            const uint32_t cnt = c0 + c1 + c2 + c3;
+            const uint32_t incl = wave_inclusive_sum32(cnt);
+            if (l == kWave - 1) s_wsum[h] = incl;
+            helper_barrier(&s_sync[0], gen);
+            uint32_t base = 0, total = 0;
+#pragma unroll
+            for (uint32_t w = 0; w < kIdxHelpers; w++) {
+                const uint32_t sw = s_wsum[w];
+                base += w < h ? sw : 0;
+                total += sw;
+            }
+            if (ht < kIdxPieces) {
+                const uint32_t ex = base + incl - cnt;
+                reinterpret_cast<uint4 *>(s_before)[ht] =
+                    make_uint4(ex, ex + c0, ex + c0 + c1, ex + c0 + c1 + c2);
+                uint32_t r = ex;
+#pragma unroll
+                for (uint32_t i = 0; i < 4; i++) {
+                    uint32_t m = tb[i];
+                    while (m) {
+                        const uint32_t bb = (uint32_t)__builtin_ctz(m);
+                        m &= m - 1;
+                        s_tpos[r++] = (uint16_t)(16 * ht + 4 * i + bb);
+                    }
+                }
+            }
+            // Entries go to buffer t & 1, which held window t - 2: wait
+            // until the walker is done with it.
+            if (t >= 2) {
+                while (lds_load_acquire(&s_sync[2]) < t - 1 && !lds_load_acquire(&s_sync[3]))
+                    __builtin_amdgcn_s_sleep(1);
+            }
+            helper_barrier(&s_sync[0], gen);
+            // Terminators before region byte x.
+            auto tcount = [&](uint32_t x) {
+                const uint32_t wd = buf[x >> 2];
+                return s_before[x >> 2] + __builtin_popcount(term_bits(wd) & ((1u << (x & 3)) - 1));
+            };
+            uint32_t *ent = s_ent[t & 1];
+            for (uint32_t p = ht; p < kIdxStep; p += kWave * kIdxHelpers) {
+                const uint32_t hb = (buf[p >> 2] >> (8 * (p & 3))) & 0xff;
+                uint32_t e_out;
+                if (hb < 128) {
+                    // Run: header, delta byte, base varint from r to terminator e.
+                    const uint32_t r = p + 2, ti = tcount(r);
+                    const uint32_t e = ti < total ? s_tpos[ti] : kIdxRegion;
+                    const uint32_t nb = e - r + 1;
+                    uint32_t code = kEntOk;
+                    if (W + r > end) code = kEntTruncated;
+                    else if (nb > 10 || (nb == 10 && ((buf[e >> 2] >> (8 * (e & 3))) & 0xff) > 1))
+                        code = kEntCorrupt;
+                    else if (W + e >= end) code = kEntTruncated;
+                    e_out = make_ent(code == kEntOk ? e + 1 - p : 0, hb + 3, code);
+                } else {
+                    // Literal list of 256 - hb varints: ends at its last terminator.
+                    const uint32_t cntl = 256 - hb, ti = tcount(p + 1) + cntl - 1;
+                    const uint32_t e = ti < total ? s_tpos[ti] : kIdxRegion;
+                    const bool open = e >= kIdxRegion || W + e >= end;
+                    e_out = make_ent(open ? 0 : e + 1 - p, cntl, open ? kEntOpen : kEntOk);
+                }
+                ent[p] = e_out;
+            }
+            helper_barrier(&s_sync[0], gen);
+            if (h == 0 && l == 0) lds_store_release(&s_sync[1], t + 1);  // window t ready
         }
-    };
-    issue(0);
+        wait_vm();  // a load issued one window ahead may still be landing
+        return;
+    }
 
-    // Walker state (wave 0, wave-uniform), and per lane j < kSplitWaves the
+    // ---- walker (wave 0): wave-uniform state; per lane j < kSplitWaves the
     // first group of range j and where it starts.
+    __builtin_amdgcn_s_setprio(3);
     uint32_t pos = skip, nv = 0, k = 0, j = 0, next = 0;
     uint32_t rg = 0, rpos = 0, rnv = 0;
     unsigned long long key = ~0ull;
     bool open_end = false;
-
     for (uint32_t t = 0;; t++) {
         const uint32_t W = t * kIdxStep;
-        uint32_t *buf = s_buf[t & 1];
-        wait_vm();
-        __syncthreads();  // every wave's share of the region has landed
-        // Bytes past the end of the chunk read as zero (terminators).
-        for (uint32_t q = tid; q < kIdxPieces; q += kWave * kIdxWaves) {
-            const uint32_t at = W + 16 * q;
-            if (at + 16 > end) {
-                uint4 v = reinterpret_cast<uint4 *>(buf)[q];
-                const uint32_t valid = at < end ? end - at : 0;
-                uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int i = 0; i < 4; i++) {
-                    const int keep = (int)valid - 4 * i;
-                    w[i] &= keep >= 4 ? 0xffffffffu : keep <= 0 ? 0u : ((1u << (8 * keep)) - 1);
-                }
-                reinterpret_cast<uint4 *>(buf)[q] = make_uint4(w[0], w[1], w[2], w[3]);
+        bool done = false;
+        // Leave windows behind without waiting for them (a group jump
+        // never passes a whole window, but an empty chunk starts past 0).
+        if (nv < cap && pos < end && pos < W + kIdxStep) wait_at_least(&s_sync[1], t + 1);
+        const uint32_t *ent = s_ent[t & 1];
+        while (true) {
+            if (nv >= cap) {
+                done = true;
+                break;
             }
-        }
-        if (W + kIdxStep < end) issue(t + 1);  // the other buffer: its window is done
-        __syncthreads();
-        // Terminator counts: thread tid takes region bytes [16 tid, 16 tid + 16).
-        uint32_t flags = 0;
-        if (tid < kIdxPieces) {
-            const uint4 v = reinterpret_cast<const uint4 *>(buf)[tid];
-            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int i = 0; i < 4; i++) {
-                const uint32_t tm = (~w[i] & 0x80808080u) >> 7;  // bits 0, 8, 16, 24
-                flags |= ((tm | (tm >> 7) | (tm >> 14) | (tm >> 21)) & 15) << (4 * i);
+            if (pos >= end) {
+                key = error_key(k, CODAG_E_TRUNCATED);
+                done = true;
+                break;
             }
-        }
-        const uint32_t cnt = __builtin_popcount(flags);
-        const uint32_t incl = wave_inclusive_sum32(cnt);
-        if (l == kWave - 1) s_wsum[wave] = incl;
-        __syncthreads();
-        uint32_t before = 0, total = 0;
-#pragma unroll
-        for (uint32_t w = 0; w < kIdxWaves; w++) {
-            const uint32_t sw = s_wsum[w];
-            before += w < wave ? sw : 0;
-            total += sw;
-        }
-        if (tid < kIdxPieces) {
-            const uint32_t ex = before + incl - cnt;
-#pragma unroll
-            for (uint32_t b = 0; b < 16; b++) {
-                const uint32_t r = ex + __builtin_popcount(flags & ((1u << b) - 1));
-                s_tcount[16 * tid + b] = (uint16_t)r;
-                if ((flags >> b) & 1) s_tpos[r] = (uint16_t)(16 * tid + b);
+            if (pos >= W + kIdxStep) break;  // on in the next window
+            const uint32_t e = uni(ent[pos - W]);
+            const uint32_t code = e >> 21, len = (e >> 13) & 0xff, off = e & 0x1fff;
+            if (code == kEntTruncated || code == kEntCorrupt) {
+                key = error_key(k, code == kEntTruncated ? CODAG_E_TRUNCATED : CODAG_E_CORRUPT);
+                done = true;
+                break;
             }
-        }
-        __syncthreads();
-        // The group that would start at each position of the window.
-        for (uint32_t p = tid; p < kIdxStep; p += kWave * kIdxWaves) {
-            const uint32_t h = lds_byte(buf, p);
-            uint32_t ent;
-            if (h < 128) {
-                // Run: header, delta byte, base varint from r to terminator e.
-                const uint32_t r = p + 2, ti = s_tcount[r];
-                const uint32_t e = ti < total ? s_tpos[ti] : kIdxRegion;
-                const uint32_t nb = e - r + 1;
-                uint32_t code = kEntOk;
-                if (W + r > end) code = kEntTruncated;
-                else if (nb > 10 || (nb == 10 && lds_byte(buf, e) > 1)) code = kEntCorrupt;
-                else if (W + e >= end) code = kEntTruncated;
-                ent = make_ent(code == kEntOk ? e + 1 - p : 0, h + 3, code);
-            } else {
-                // Literal list of 256 - h varints: ends at its last terminator.
-                const uint32_t cntl = 256 - h, ti = s_tcount[p + 1] + cntl - 1;
-                const uint32_t e = ti < total ? s_tpos[ti] : kIdxRegion;
-                const bool open = e >= kIdxRegion || W + e >= end;
-                ent = make_ent(open ? 0 : e + 1 - p, cntl, open ? kEntOpen : kEntOk);
+            if (nv + len > cap) {
+                key = error_key(k, CODAG_E_OVERFLOW);
+                done = true;
+                break;
             }
-            s_ent[p] = ent;
-        }
-        __syncthreads();
-        // The walk, by wave 0.
-        if (wave == 0) {
-            bool done = false;
-            while (true) {
-                if (nv >= cap) {
-                    done = true;
-                    break;
-                }
-                if (pos >= end) {
-                    key = error_key(k, CODAG_E_TRUNCATED);
-                    done = true;
-                    break;
-                }
-                if (pos >= W + kIdxStep) break;  // on in the next window
-                const uint32_t e = uni(s_ent[pos - W]);
-                const uint32_t code = e >> 21, len = (e >> 13) & 0xff, off = e & 0x1fff;
-                if (code == kEntTruncated || code == kEntCorrupt) {
-                    key = error_key(k, code == kEntTruncated ? CODAG_E_TRUNCATED : CODAG_E_CORRUPT);
-                    done = true;
-                    break;
-                }
-                if (nv + len > cap) {
-                    key = error_key(k, CODAG_E_OVERFLOW);
-                    done = true;
-                    break;
-                }
-                const uint32_t gp = pos, gn = nv;
-                nv += len;
-                // Ranges that start at or before this group's first value start here.
-                while (j < kSplitWaves && gn >= next) {
-                    rg = l == j ? k : rg;
-                    rpos = l == j ? gp : rpos;
-                    rnv = l == j ? gn : rnv;
-                    j++;
-                    next = cap * j / kSplitWaves;  // cap < 2^28
-                }
-                k++;
-                if (code == kEntOpen) {
-                    // A list that does not end inside the chunk is still
-                    // recorded: its decode reports where it fails.
-                    open_end = true;
-                    done = true;
-                    break;
-                }
-                pos += off;
+            const uint32_t gp = pos, gn = nv;
+            nv += len;
+            // Ranges that start at or before this group's first value start here.
+            while (j < kSplitWaves && gn >= next) {
+                rg = l == j ? k : rg;
+                rpos = l == j ? gp : rpos;
+                rnv = l == j ? gn : rnv;
+                j++;
+                next = cap * j / kSplitWaves;  // cap < 2^28
             }
-            if (l == 0) s_done = done ? 1u : 0u;
+            k++;
+            if (code == kEntOpen) {
+                // A list that does not end inside the chunk is still
+                // recorded: its decode reports where it fails.
+                open_end = true;
+                done = true;
+                break;
+            }
+            pos += off;
         }
-        __syncthreads();
-        if (s_done) break;
-    }
-    if (wave != 0) {
-        wait_vm();  // a load issued one window ahead may still be landing
-        return;
+        if (done) {
+            if (l == 0) lds_store_release(&s_sync[3], 1u);
+            break;
+        }
+        if (l == 0) lds_store_release(&s_sync[2], t + 1);  // window t walked
     }
     if (!open_end && key == ~0ull && pos != end) key = error_key(k, CODAG_E_CORRUPT);
     // Ranges not started are empty; each ends where the next one starts.
@@ -309,7 +373,7 @@ int launch_rle_v1_split(const uint8_t *comp, const uint64_t *coff, uint8_t *out,
     uint4 *range = static_cast<uint4 *>(ws);
     unsigned long long *keys =
         reinterpret_cast<unsigned long long *>(static_cast<char *>(ws) + range_bytes);
-    hipLaunchKernelGGL(rle_v1_index, dim3(n), dim3(kWave * kIdxWaves), 0, s, comp, coff, out, ooff, n,
+    hipLaunchKernelGGL(rle_v1_index, dim3(n), dim3(kIdxThreads), 0, s, comp, coff, out, ooff, n,
                        range, keys);
     const uint32_t gb = (n * kSplitWaves + kSplitWpb - 1) / kSplitWpb;
     hipLaunchKernelGGL(rle_v1_groups, dim3(gb), dim3(kWave * kSplitWpb), 0, s, comp, coff, out,
@@ -379,6 +443,44 @@ __device__ __forceinline__ int v2_index_short_repeats(Ring &in, uint32_t &pos, u
         const uint32_t h = (in.word(at_b >> 2) >> (8 * (at_b & 3))) & 0xff;
         const uint32_t w = ((h >> 3) & 7) + 1, cs = (h & 7) + 3;
         const uint32_t nxt = (h >> 6) == 0 && at_b + 1 + w <= end ? l + 1 + w : 128 + l;
+        // Fast path: the chain walked with one lane read per run carrying
+        // both the link and the run's value count; a window that holds no
+        // range start and stays inside the output needs nothing else.
+        {
+            const uint32_t link = nxt < 128 ? nxt | (cs << 8) : nxt;
+            uint32_t t = 0, acc = nv;
+            for (;;) {
+                uint32_t v = readlane(link, t);
+                t = v & 0xff;
+                acc += v >> 8;
+                if (t >= kWave) break;
+                v = readlane(link, t);
+                t = v & 0xff;
+                acc += v >> 8;
+                if (t >= kWave) break;
+            }
+            if (acc <= cap && (j >= kV2Ranges || v2_threshold(cap, j) >= acc)) {
+                nv = acc;
+                if (t >= 128) {
+                    t -= 128;
+                    int st = CODAG_OK;
+                    if (pos + t < end && nv < cap) {
+                        const uint32_t hs = readlane(h, t);
+                        if ((hs >> 6) == 0) {
+                            st = nv + (hs & 7) + 3 > cap ? CODAG_E_OVERFLOW : CODAG_E_TRUNCATED;
+                            errnv = nv;
+                        }
+                    }
+                    pos += t;
+                    return st;
+                }
+                pos += t;
+                if (nv >= cap || pos >= end) return CODAG_OK;
+                continue;
+            }
+        }
+        // The window fills the output or holds a range start: every run's
+        // first value, by a prefix sum over the lanes where runs start.
         uint32_t s = 0;
         uint64_t starts = 0;
         do {
