@@ -68,14 +68,43 @@ enum {
  *                     path takes its workspace (272 bytes per RLE v1 chunk,
  *                     96 per RLE v2 chunk) from the stream-ordered allocator
  *                     (hipMallocAsync) on `stream`.  Ignored for Deflate.
+ *   variant           0 = the decoders above.  The others are the decoding-
+ *                     unit designs CODAG measures its own against, for
+ *                     comparison on the same chunks (same output and
+ *                     statuses; no chunk_ticks; waves_per_block,
+ *                     group_parallel, lit_table_bits and history_kib are
+ *                     ignored -- Deflate uses 9 table bits and a 4 KiB
+ *                     window):
+ *                       CODAG_VARIANT_LEADER_LANE (Section V-E, single-
+ *                       thread decoding): one lane of each chunk's wave
+ *                       parses every header, varint and Huffman token and
+ *                       hands each result to the wave through LDS; the
+ *                       other lanes only write.  RLE v1 and Deflate.
+ *                       CODAG_VARIANT_PREFETCH_WAVE (Section V-F): a second
+ *                       wave per chunk loads the input into an LDS ring
+ *                       ahead of the decoding wave, which runs the main
+ *                       one-wave decoder.  RLE v1 and Deflate.
+ *                       CODAG_VARIANT_BLOCK_LEADER (Section II-C): a
+ *                       256-thread workgroup per chunk; thread 0 parses each
+ *                       group while the others wait at a barrier, then all
+ *                       write it.  RLE v1 only.
+ *                     Other codecs, or a variant a codec lacks, return
+ *                     CODAG_E_INVALID_ARGUMENT.
  */
+enum {
+    CODAG_VARIANT_DEFAULT = 0,
+    CODAG_VARIANT_LEADER_LANE = 1,
+    CODAG_VARIANT_PREFETCH_WAVE = 2,
+    CODAG_VARIANT_BLOCK_LEADER = 3
+};
 typedef struct codag_opts {
     int waves_per_block;
     int lit_table_bits;
     uint64_t *chunk_ticks;
     int history_kib;
     int group_parallel;
-    int reserved[6];
+    int variant;
+    int reserved[5];
 } codag_opts;
 
 /*

@@ -18,6 +18,7 @@ RLE_V1, RLE_V2, DEFLATE = 1, 2, 3
 ORDER_INDEX, ORDER_GIVEN, ORDER_LEARNED = 0, 1, 2
 SCHED_FEATURES, SCHED_PARAMS, SCHED_NORM = 16, 5313, 34
 OK = 0
+VARIANT_DEFAULT, VARIANT_LEADER_LANE, VARIANT_PREFETCH_WAVE, VARIANT_BLOCK_LEADER = 0, 1, 2, 3
 E_INVALID_ARGUMENT, E_HIP, E_CORRUPT, E_TRUNCATED, E_OVERFLOW, E_UNDERFLOW = -1, -2, -3, -4, -5, -6
 
 _lib = None
@@ -33,7 +34,8 @@ class CodagError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_int), ("lit_table_bits", ctypes.c_int),
                 ("chunk_ticks", ctypes.c_void_p), ("history_kib", ctypes.c_int),
-                ("group_parallel", ctypes.c_int), ("reserved", ctypes.c_int * 6)]
+                ("group_parallel", ctypes.c_int), ("variant", ctypes.c_int),
+                ("reserved", ctypes.c_int * 5)]
 
 
 class BatchOpts(ctypes.Structure):
@@ -120,7 +122,7 @@ def _check_dev(t, name, dtype=None, n=None):
 
 def decompress(codec: int, comp, chunk_offsets, out, out_offsets, *, status=None,
                waves_per_block: int = 0, lit_table_bits: int = 0, history_kib: int = 0,
-               group_parallel: int = 0, chunk_ticks=None, stream=None) -> None:
+               group_parallel: int = 0, chunk_ticks=None, variant: int = 0, stream=None) -> None:
     """Enqueue codag_decompress_ex on `stream` (default: torch's current stream).
 
     comp: uint8 device tensor; chunk_offsets/out_offsets: int64 device tensors of
@@ -128,11 +130,12 @@ def decompress(codec: int, comp, chunk_offsets, out, out_offsets, *, status=None
     tensor of n_chunks; chunk_ticks: optional int64 device tensor of n_chunks.
     """
     _decompress("codag_decompress_ex", codec, comp, chunk_offsets, out, out_offsets, status,
-                waves_per_block, lit_table_bits, history_kib, group_parallel, chunk_ticks, stream)
+                waves_per_block, lit_table_bits, history_kib, group_parallel, chunk_ticks, variant,
+                stream)
 
 
 def _decompress(entry, codec, comp, chunk_offsets, out, out_offsets, status, waves_per_block,
-                lit_table_bits, history_kib, group_parallel, chunk_ticks, stream):
+                lit_table_bits, history_kib, group_parallel, chunk_ticks, variant, stream):
     import torch
     n = chunk_offsets.numel() - 1
     if n < 0 or out_offsets.numel() != n + 1:
@@ -144,7 +147,8 @@ def _decompress(entry, codec, comp, chunk_offsets, out, out_offsets, status, wav
     d = _check_dev(out_offsets, "out_offsets", offs)
     s = _check_dev(status, "status", (torch.int32,), n)
     t = _check_dev(chunk_ticks, "chunk_ticks", (torch.int64,), n)
-    opts = Opts(waves_per_block, lit_table_bits, t, history_kib, group_parallel, (ctypes.c_int * 6)())
+    opts = Opts(waves_per_block, lit_table_bits, t, history_kib, group_parallel, variant,
+                (ctypes.c_int * 5)())
     rc = getattr(lib(), entry)(int(codec), a, b, c, d, n, _stream_handle(stream), s,
                                ctypes.byref(opts))
     if rc != OK:
@@ -153,12 +157,14 @@ def _decompress(entry, codec, comp, chunk_offsets, out, out_offsets, status, wav
 
 def decompress_noalloc(codec: int, comp, chunk_offsets, out, out_offsets, *, status=None,
                        waves_per_block: int = 0, lit_table_bits: int = 0, history_kib: int = 0,
-                       group_parallel: int = 0, chunk_ticks=None, stream=None) -> None:
+                       group_parallel: int = 0, chunk_ticks=None, variant: int = 0,
+                       stream=None) -> None:
     """Enqueue codag_decompress_noalloc (arguments as decompress()): the same
     decode with every workspace in the library's static per-device scratch
     array; calls that overlap in time on one device must not be made."""
     _decompress("codag_decompress_noalloc", codec, comp, chunk_offsets, out, out_offsets, status,
-                waves_per_block, lit_table_bits, history_kib, group_parallel, chunk_ticks, stream)
+                waves_per_block, lit_table_bits, history_kib, group_parallel, chunk_ticks, variant,
+                stream)
 
 
 def get_error(stream=None):

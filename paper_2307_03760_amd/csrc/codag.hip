@@ -161,10 +161,16 @@ int decompress(int codec, const uint8_t *comp_buf, const uint64_t *chunk_offsets
         (hist != 2 && hist != 4 && hist != 8 && hist != 16 && hist != 32))
         return CODAG_E_INVALID_ARGUMENT;
     uint64_t *ticks = opts ? opts->chunk_ticks : nullptr;
+    const int variant = opts ? opts->variant : 0;
+    if (variant < 0 || variant > CODAG_VARIANT_BLOCK_LEADER || (variant && ticks))
+        return CODAG_E_INVALID_ARGUMENT;
     DeviceState *ds = nullptr;
     int st = device_state(&ds);
     if (st) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (variant)
+        return launch_variant(variant, codec, comp_buf, chunk_offsets, out_buf, out_offsets,
+                              (uint32_t)n_chunks, chunk_status, ds->err, s);
     switch (codec) {
         case CODAG_RLE_V1: {
             const int gp = opts ? opts->group_parallel : 0;

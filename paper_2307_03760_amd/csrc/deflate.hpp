@@ -184,8 +184,9 @@ struct BitIn {
                      // 32 bits because there is no scalar 64-bit ordered
                      // compare (chunks are below 256 MiB)
 
-    __device__ __forceinline__ void seek(InRing &in, uint32_t pos) {
-        if (pos >= in.loaded + kFetchBytes) in.restart(pos);
+    template <class Ring>
+    __device__ __forceinline__ void seek(Ring &in, uint32_t pos) {
+        if (pos >= in.loaded + Ring::kFetch) in.restart(pos);
         uint32_t a = pos & ~3u;
         in.ensure(a + 4);
         uint32_t w = uni(in.word(a >> 2));
@@ -195,7 +196,8 @@ struct BitIn {
         next = a + 4;
         remain = 8 * ((int32_t)in.gend - (int32_t)pos);
     }
-    __device__ __forceinline__ void refill(InRing &in) {
+    template <class Ring>
+    __device__ __forceinline__ void refill(Ring &in) {
         if (cnt <= 32) {
             if (in.loaded < next + 4) in.ensure(next + 4);
             uint32_t w = uni(in.word(next >> 2));
@@ -222,7 +224,8 @@ struct BitIn {
     }
     // Refill with at most one ring advance (the reader moves 4 bytes at a
     // time, the ring 1 KiB), keeping the hot loop free of inner loops.
-    __device__ __forceinline__ void refill1(InRing &in) {
+    template <class Ring>
+    __device__ __forceinline__ void refill1(Ring &in) {
         if (cnt <= 32) {
             if (in.loaded < next + 4) in.commit();
             uint32_t w = uni(in.word(next >> 2));
@@ -368,7 +371,8 @@ struct WindowOut {
 // Reads a dynamic block's header up to its code lengths (RFC 1951 3.2.7):
 // HLIT, HDIST, HCLEN, the code-length code (built into cltab, 7-bit
 // table), then the HLIT + HDIST lengths into lens.  Returns a status.
-__device__ __forceinline__ int read_code_lengths(InRing &in, BitIn &bi, uint16_t *cltab,
+template <class Ring>
+__device__ __forceinline__ int read_code_lengths(Ring &in, BitIn &bi, uint16_t *cltab,
                                                  CodeMeta *meta, uint16_t *sorted, uint8_t *lens,
                                                  uint32_t &hlit, uint32_t &hdist, uint32_t &hclen) {
     const uint32_t l = lane();
@@ -435,8 +439,8 @@ constexpr int kMore = 1;
 // The loop is kept small and with few exits: literals first, then
 // length/distance pairs; everything rare leaves the loop.  With ONE, it
 // returns kMore after the first literal or copy.
-template <int TB, uint32_t H, bool ONE = false>
-__device__ __forceinline__ int inflate_symbols(InRing &in, BitIn &bi, WindowOut<H> &o,
+template <int TB, uint32_t H, bool ONE = false, class Ring>
+__device__ __forceinline__ int inflate_symbols(Ring &in, BitIn &bi, WindowOut<H> &o,
                                                DeflateLds<TB, H> *lds, bool have_dist,
                                                uint32_t len_tab, uint32_t dist_tab) {
     int st;
@@ -580,8 +584,8 @@ __device__ __forceinline__ void lane_token(uint32_t s0, uint32_t s1, uint32_t s2
     }
 }
 
-template <int TB, uint32_t H>
-__device__ __forceinline__ int inflate_batched(InRing &in, BitIn &bi, WindowOut<H> &o,
+template <int TB, uint32_t H, class Ring>
+__device__ __forceinline__ int inflate_batched(Ring &in, BitIn &bi, WindowOut<H> &o,
                                                DeflateLds<TB, H> *lds, bool have_dist,
                                                uint32_t len_tab, uint32_t dist_tab) {
     const uint32_t l = lane();
@@ -738,8 +742,64 @@ __device__ __forceinline__ int inflate_batched(InRing &in, BitIn &bi, WindowOut<
     }
 }
 
-template <int TB, uint32_t H>
-__device__ __forceinline__ int decode_deflate(InRing &in, uint8_t *out, uint32_t cap,
+// Leader-lane symbol loop: lane 0 decodes the token at the current bit
+// position (the same per-lane token decoder the batched path runs on every
+// lane), writes it to an LDS slot, and the wave reads it back and writes the
+// literal or copy.  Every token takes one decode by one lane and one LDS
+// round trip.  Anything but a plain literal or an in-range copy goes through
+// one step of the symbol-at-a-time loop, so statuses are that loop's.
+template <int TB, uint32_t H, class Ring>
+__device__ __forceinline__ int inflate_leader(Ring &in, BitIn &bi, WindowOut<H> &o,
+                                              DeflateLds<TB, H> *lds, bool have_dist,
+                                              uint32_t len_tab, uint32_t dist_tab) {
+    uint32_t p = 8 * bi.next - bi.cnt;  // bit position of the next code
+    uint32_t *slot = reinterpret_cast<uint32_t *>(lds->lens);  // free while symbols decode
+    for (;;) {
+        const uint32_t wi = p >> 5;
+        in.ensure(4 * (wi + 5) + 4);
+        if (lane() == 0) {
+            uint32_t info, dist;
+            lane_token<TB, H>(in.word(wi), in.word(wi + 1), in.word(wi + 2), in.word(wi + 3),
+                              in.word(wi + 4), p, lds, have_dist, info, dist);
+            slot[0] = info;
+            slot[1] = dist;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t info = uni(slot[0]), dist = uni(slot[1]);
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t bits = (info >> 8) & 63;
+        if (!(info & kTokStop)) {
+            if (!(info & kTokCopy)) {
+                if (o.pos < o.cap) {
+                    o.put_literal(info & 0xff);
+                    p += bits;
+                    continue;
+                }
+            } else {
+                const uint32_t len = info >> 16;
+                if (dist <= o.pos && o.pos + len <= o.cap) {
+                    o.copy(dist, len);
+                    p += bits;
+                    continue;
+                }
+            }
+        }
+        bi.seek(in, p >> 3);
+        bi.skip(p & 7);
+        int st = inflate_symbols<TB, H, true>(in, bi, o, lds, have_dist, len_tab, dist_tab);
+        if (st != kMore) return st;
+        p = 8 * bi.next - bi.cnt;
+    }
+}
+
+// MODE kAllLanes: the batched token decoder above (every lane decodes a
+// candidate token); kLeaderLane: lane 0 alone decodes each token and hands
+// it to the wave through LDS (the single-thread decoding CODAG compares
+// against, Section V-E).
+enum : int { kAllLanes = 0, kLeaderLane = 1 };
+
+template <int TB, uint32_t H, int MODE = kAllLanes, class Ring>
+__device__ __forceinline__ int decode_deflate(Ring &in, uint8_t *out, uint32_t cap,
                                               DeflateLds<TB, H> *lds) {
     const uint32_t l = lane();
     BitIn bi;
@@ -821,7 +881,10 @@ __device__ __forceinline__ int decode_deflate(InRing &in, uint8_t *out, uint32_t
                 }
                 have_dist = dr.total != 0;
             }
-            st = inflate_batched<TB, H>(in, bi, o, lds, have_dist, len_tab, dist_tab);
+            if constexpr (MODE == kLeaderLane)
+                st = inflate_leader<TB, H>(in, bi, o, lds, have_dist, len_tab, dist_tab);
+            else
+                st = inflate_batched<TB, H>(in, bi, o, lds, have_dist, len_tab, dist_tab);
             if (st) break;
         }
         if (last) break;

@@ -47,6 +47,11 @@ constexpr uint64_t kSplitV2MaxChunks = 2048;
 // bytes), two 8-byte error keys.
 constexpr size_t kSplitV2WorkspacePerChunk = 8 * 8 + 16 + 2 * 8;
 
+// The decoding-unit ablations (codag_opts.variant != 0), on stream s.
+int launch_variant(int variant, int codec, const uint8_t *comp, const uint64_t *coff, uint8_t *out,
+                   const uint64_t *ooff, uint32_t n, int32_t *status, unsigned long long *err,
+                   hipStream_t s);
+
 // Arguments of one batched launch (a captured graph is reused while they
 // stay the same).
 struct BatchArgs {

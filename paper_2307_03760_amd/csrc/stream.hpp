@@ -174,4 +174,99 @@ __device__ __forceinline__ void store_bytes(uint8_t *p, uint32_t v, uint32_t n) 
     for (uint32_t k = 0; k < n; k++) p[k] = (uint8_t)(v >> (8 * k));
 }
 
+// input_stream of the prefetch-wave ablation (CODAG Section V-F): a second
+// wave of the workgroup loads the chunk into an LDS ring of kPrefetchSlots
+// kilobytes, as far ahead of the decoding wave as the ring allows, and the
+// decoding wave only waits for bytes to arrive.  The two waves meet through
+// LDS counters: `filled` (bytes loaded, set by the loader) and `need` (the
+// decoder's read frontier).  The decoder's side has the InRing interface.
+constexpr uint32_t kPrefetchSlots = 4;
+struct PrefetchShared {
+    uint32_t ring[kPrefetchSlots * 256 + 4];  // + mirror of the first 16 bytes
+    uint32_t filled, need, done;
+};
+
+__device__ __forceinline__ uint32_t lds_acquire(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_release(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+struct PrefetchRing {
+    static constexpr uint32_t kFetch = 1024, kBytes = kPrefetchSlots * kFetch, kWords = kBytes / 4;
+    uint32_t skip, gend, loaded;  // loaded: bytes known to be in the ring
+    PrefetchShared *sh;
+
+    __device__ __forceinline__ void init(const uint8_t *chunk, uint32_t len, PrefetchShared *s) {
+        skip = (uint32_t)(reinterpret_cast<uintptr_t>(chunk) & 15);
+        gend = skip + len;
+        loaded = 0;
+        sh = s;
+    }
+    // Bytes [end - 2 KiB, end) readable: publish the frontier, wait for the loader.
+    __device__ __forceinline__ void ensure(uint32_t end) {
+        if (loaded >= end) return;
+        if (lane() == 0) lds_release(&sh->need, end);
+        while ((loaded = uni(lds_acquire(&sh->filled))) < end) __builtin_amdgcn_s_sleep(1);
+    }
+    __device__ __forceinline__ void commit() { ensure(loaded + kFetch); }
+    __device__ __forceinline__ void restart(uint32_t) {}  // the loader streams every byte anyway
+    __device__ __forceinline__ void finish() {
+        if (lane() == 0) lds_release(&sh->done, 1u);
+    }
+    __device__ __forceinline__ uint32_t word(uint32_t w) const { return sh->ring[w & (kWords - 1)]; }
+    __device__ __forceinline__ uint32_t word_next(uint32_t w) const {
+        return sh->ring[(w & (kWords - 1)) + 1];
+    }
+    __device__ __forceinline__ uint32_t word_at(uint32_t w, uint32_t k) const {
+        return sh->ring[(w & (kWords - 1)) + k];
+    }
+    __device__ __forceinline__ uint64_t peek8(uint32_t pos) const {
+        uint32_t w = pos >> 2;
+        uint32_t a = word_at(w, 0), b = word_at(w, 1), c = word_at(w, 2);
+        uint32_t sh8 = 8 * (pos & 3);
+        uint64_t lo = ((uint64_t)b << 32) | a;
+        uint64_t r = sh8 ? (lo >> sh8) | ((uint64_t)c << (64 - sh8)) : lo;
+        return uni64(r);
+    }
+};
+
+// The loader wave: kilobyte k of the chunk's 16-byte hull goes to slot
+// k % kPrefetchSlots once the decoder no longer reads the kilobyte it held
+// (its frontier is at least (k - 1) KiB: the decoder reads at most 2 KiB
+// behind its frontier).  Bytes past the chunk read as zero, and the loader
+// keeps supplying zero kilobytes past the end (decoders read a little
+// beyond the last byte) until the decoder says it is done.
+__device__ __forceinline__ void prefetch_loader(const uint8_t *chunk, uint32_t len, PrefetchShared *sh) {
+    const uint32_t skip = (uint32_t)(reinterpret_cast<uintptr_t>(chunk) & 15);
+    const uint8_t *gbase = chunk - skip;
+    const uint32_t gend = skip + len, l = lane();
+    for (uint32_t k = 0;; k++) {
+        if (k >= kPrefetchSlots) {
+            while (lds_acquire(&sh->need) < (k - 1) * PrefetchRing::kFetch && !lds_acquire(&sh->done))
+                __builtin_amdgcn_s_sleep(1);
+        }
+        if (lds_acquire(&sh->done)) break;
+        const uint32_t at = k * PrefetchRing::kFetch + 16 * l;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (at < gend) v = *reinterpret_cast<const uint4 *>(gbase + at);
+        if (at + 16 > gend) {
+            const uint32_t valid = at < gend ? gend - at : 0;
+            uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int keep = (int)valid - 4 * j;
+                w[j] &= keep >= 4 ? 0xffffffffu : keep <= 0 ? 0u : ((1u << (8 * keep)) - 1);
+            }
+            v = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        const uint32_t s = k % kPrefetchSlots;
+        reinterpret_cast<uint4 *>(sh->ring)[s * 64 + l] = v;
+        if (s == 0 && l == 0) reinterpret_cast<uint4 *>(sh->ring)[kPrefetchSlots * 64] = v;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        if (l == 0) lds_release(&sh->filled, (k + 1) * PrefetchRing::kFetch);
+    }
+}
+
 }  // namespace codag
