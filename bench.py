@@ -315,6 +315,39 @@ def time_workload(name, ch, steps, warmup, dev, flush_buf=None):
     return res, out
 
 
+ABLATIONS = {  # codag_opts.variant per decoding-unit design (the paper's Sections V-E, V-F, II-C)
+    "all_lanes_one_wave": 0,
+    "leader_lane": 1,
+    "prefetch_wave": 2,
+    "block_leader": 3,
+}
+
+
+def time_ablations(ch, dev, steps=3, warmup=1):
+    """The decoding-unit designs on the same chunks: the main one-wave decoder
+    (group_parallel off) against the leader-lane, prefetch-wave and (RLE v1)
+    block-leader variants.  Each launch is checked for success."""
+    import numpy as np
+    import torch
+    import paper_2307_03760_amd as codag
+    codec = int(ch.codecs[0])
+    comp = torch.from_numpy(ch.comp).to(dev)
+    co = torch.from_numpy(ch.chunk_offsets.view(np.int64)).to(dev)
+    oo = torch.from_numpy(ch.out_offsets.view(np.int64)).to(dev)
+    out = torch.empty(ch.out_bytes, dtype=torch.uint8, device=dev)
+    st = torch.full((ch.n_chunks,), 99, dtype=torch.int32, device=dev)
+    res = {}
+    for name, variant in ABLATIONS.items():
+        if variant == 3 and codec != 1:
+            continue
+        kw = {"variant": variant} if variant else {"group_parallel": 1}
+        st.fill_(99)
+        ms = _time_launches(lambda: codag.decompress(codec, comp, co, out, oo, status=st, **kw), steps, warmup)
+        _check_batch(codag, st, f"ablation {name}")
+        res[name] = {"ms": ms, "gbps": ch.out_bytes / (ms * 1e-3) / 1e9}
+    return res
+
+
 def cpu_baseline(name, ch, gpu_out, budget_s, threads=None):
     """The oracle on a bounded sample of the workload's chunks, on `threads`
     host threads (default: the host's share of cores)."""
@@ -395,6 +428,8 @@ def main():
                     help="oracle time for the headline baseline (the per-codec oracle timings "
                          "under per_workload take a quarter of it per thread count)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ablations", action="store_true",
+                    help="skip the decoding-unit ablations (leader lane, prefetch wave, block leader)")
     ap.add_argument("--json-out", default="")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of this many MiB (a reference "
@@ -447,6 +482,8 @@ def main():
             torch.cuda.empty_cache()
         else:
             r, o = time_workload(name, c2, args.steps, args.warmup, dev, flush)
+            if name in ("rle_v1", "rle_v1_scaled", "deflate") and not args.no_ablations:
+                r["ablations"] = time_ablations(c2, dev)
             if not args.no_cpu_baseline and name in ("rle_v1", "deflate"):
                 o_np = o.cpu().numpy()
                 r["cpu_oracle"] = {

@@ -5,9 +5,10 @@ parity.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg
 of ``bench.py`` may import this package; the GPU library and its Python
 binding never do, and share no code, header, table or constant with it.
 
-* ``oracle.c`` -- sequential decoders for ORC integer RLE v1/v2 and Deflate
-  (CODAG, Section II-A and Section V-A; bit layouts from the Apache ORC
-  integer run-length encodings and RFC 1951).
+* ``oracle.c`` -- sequential decoders for ORC integer RLE v1/v2 (signed or
+  unsigned, 1/2/4/8-byte elements), ORC byte RLE and Deflate (CODAG,
+  Section II-A and Section V-A; bit layouts from the Apache ORC
+  run-length encodings and RFC 1951), and ORC's compressed-stream framing.
 * ``mlp.py`` -- float64 forward/backward/Adam of the 16-64-64-1 cost model.
 """
 from __future__ import annotations
@@ -24,7 +25,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-RLE_V1, RLE_V2, DEFLATE = 1, 2, 3
+RLE_V1, RLE_V2, DEFLATE, BYTE_RLE = 1, 2, 3, 4
 OK, E_INVALID_ARGUMENT, E_CORRUPT, E_TRUNCATED, E_OVERFLOW, E_UNDERFLOW = 0, -1, -3, -4, -5, -6
 
 _lib = None
@@ -57,6 +58,18 @@ def _load():
                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
                                               ctypes.c_void_p]
             lib.oracle_decompress.restype = ctypes.c_int
+            lib.oracle_decompress_ex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                                 ctypes.c_void_p]
+            lib.oracle_decompress_ex.restype = ctypes.c_int
+            lib.oracle_decode_chunk_ex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                   ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                                   ctypes.c_uint64, u64p]
+            lib.oracle_decode_chunk_ex.restype = ctypes.c_int
+            lib.oracle_orc_inflate_stream.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
+                                                      ctypes.c_void_p, ctypes.c_uint64, u64p]
+            lib.oracle_orc_inflate_stream.restype = ctypes.c_int
             del u8p
             _lib = lib
     return _lib
@@ -120,3 +133,40 @@ def decompress(codec: int, comp: np.ndarray, chunk_offsets: np.ndarray,
     if any(rcs):
         raise ValueError("oracle_decompress rejected its arguments")
     return out, status
+
+
+def decompress_ex(codec: int, comp: np.ndarray, chunk_offsets: np.ndarray,
+                  out_offsets: np.ndarray, *, elem_bytes: int = 8, unsigned: bool = False,
+                  capacity: bool = False):
+    """decompress() with the element type of the RLE codecs, byte RLE, and
+    Deflate output ranges as capacities.  Returns (out, status, produced)."""
+    lib = _load()
+    comp = np.ascontiguousarray(comp, dtype=np.uint8)
+    co = np.ascontiguousarray(chunk_offsets, dtype=np.uint64)
+    oo = np.ascontiguousarray(out_offsets, dtype=np.uint64)
+    n = co.size - 1
+    total = int(oo[-1]) if n >= 0 and oo.size else 0
+    store = np.zeros(total // 8 + 2, dtype=np.uint64)
+    out = store.view(np.uint8)[:total]
+    status = np.zeros(max(n, 0), dtype=np.int32)
+    produced = np.zeros(max(n, 0), dtype=np.uint64)
+    if n <= 0:
+        return out, status, produced
+    rc = lib.oracle_decompress_ex(codec, elem_bytes, int(unsigned), int(capacity), _ptr(comp),
+                                  co.ctypes.data, store.ctypes.data, oo.ctypes.data, n,
+                                  status.ctypes.data, produced.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_decompress_ex rejected its arguments")
+    return out, status, produced
+
+
+def orc_inflate_stream(framed: bytes | np.ndarray, block_size: int, out_cap: int):
+    """One compressed ORC stream (ZLIB codec): (status, decompressed bytes)."""
+    lib = _load()
+    src = np.frombuffer(bytes(framed), dtype=np.uint8) if not isinstance(framed, np.ndarray) else framed
+    src = np.ascontiguousarray(src, dtype=np.uint8)
+    out = np.zeros(max(out_cap, 1), dtype=np.uint8)
+    made = ctypes.c_uint64(0)
+    st = lib.oracle_orc_inflate_stream(_ptr(src), src.size, block_size, out.ctypes.data, out_cap,
+                                       ctypes.byref(made))
+    return st, bytes(out[: made.value])

@@ -103,9 +103,22 @@ static int br_be(byte_reader *r, int nbytes, uint64_t *v) {
     return ORACLE_OK;
 }
 
-static void put_i64(uint8_t *out, uint64_t index, uint64_t value) {
+/* Value `index` of a column of eb-byte little-endian integers: the low eb
+ * bytes of the decoded 64-bit value (a narrower column holds values that
+ * fit its type; storing the low bytes is the cast to it). */
+static void put_elem(uint8_t *out, uint64_t index, uint64_t value, int eb) {
     int k;
-    for (k = 0; k < 8; k++) out[index * 8 + k] = (uint8_t)(value >> (8 * k));
+    for (k = 0; k < eb; k++) out[index * eb + k] = (uint8_t)(value >> (8 * k));
+}
+
+/* A value varint: zigzag for signed columns, plain for unsigned ones (ORC
+ * writes unsigned streams, such as string lengths, without zigzag). */
+static int br_value_varint(byte_reader *r, int uns, uint64_t *v) {
+    uint64_t z;
+    int st = br_uvarint(r, &z);
+    if (st) return st;
+    *v = uns ? z : (uint64_t)unzigzag(z);
+    return ORACLE_OK;
 }
 
 /* ------------------------------------------------------------------ */
@@ -119,7 +132,7 @@ static void put_i64(uint8_t *out, uint64_t index, uint64_t value) {
  * (CODAG Section II-A describes RLE v1 runs as a literal plus a length.)
  */
 static int decode_rle_v1(const uint8_t *in, uint64_t in_len, uint8_t *out,
-                         uint64_t cap_values, uint64_t *n_out) {
+                         uint64_t cap_values, uint64_t *n_out, int eb, int uns) {
     byte_reader r = {in, in_len, 0};
     uint64_t n = 0;
     int st = ORACLE_OK;
@@ -130,26 +143,26 @@ static int decode_rle_v1(const uint8_t *in, uint64_t in_len, uint8_t *out,
         if (st) goto done;
         h = (int8_t)hb;
         if (h >= 0) {
-            uint64_t len = (uint64_t)h + 3, k;
+            uint64_t len = (uint64_t)h + 3, k, base;
             uint8_t db;
-            int64_t delta, base;
+            int64_t delta;
             st = br_byte(&r, &db);
             if (st) goto done;
             delta = (int8_t)db;
-            st = br_svarint(&r, &base);
+            st = br_value_varint(&r, uns, &base);
             if (st) goto done;
             if (n + len > cap_values) { st = ORACLE_E_OVERFLOW; goto done; }
             for (k = 0; k < len; k++)
-                put_i64(out, n + k, (uint64_t)base + k * (uint64_t)delta);
+                put_elem(out, n + k, base + k * (uint64_t)delta, eb);
             n += len;
         } else {
             uint64_t len = (uint64_t)(-(int)h), k;
             if (n + len > cap_values) { st = ORACLE_E_OVERFLOW; goto done; }
             for (k = 0; k < len; k++) {
-                int64_t v;
-                st = br_svarint(&r, &v);
+                uint64_t v;
+                st = br_value_varint(&r, uns, &v);
                 if (st) goto done;
-                put_i64(out, n, (uint64_t)v);
+                put_elem(out, n, v, eb);
                 n++;
             }
         }
@@ -212,7 +225,7 @@ static int read_packed(byte_reader *r, uint64_t count, int w, uint64_t *vals) {
 }
 
 static int decode_rle_v2(const uint8_t *in, uint64_t in_len, uint8_t *out,
-                         uint64_t cap_values, uint64_t *n_out) {
+                         uint64_t cap_values, uint64_t *n_out, int eb, int uns) {
     byte_reader r = {in, in_len, 0};
     uint64_t n = 0;
     uint64_t vals[512], patches[32];
@@ -231,7 +244,7 @@ static int decode_rle_v2(const uint8_t *in, uint64_t in_len, uint8_t *out,
             if (n + len > cap_values) { st = ORACLE_E_OVERFLOW; goto done; }
             st = br_be(&r, w, &z);
             if (st) goto done;
-            for (k = 0; k < len; k++) put_i64(out, n + k, (uint64_t)unzigzag(z));
+            for (k = 0; k < len; k++) put_elem(out, n + k, uns ? z : (uint64_t)unzigzag(z), eb);
             n += len;
         } else if (type == 1) {
             /* DIRECT: width code in bits 5..1, 9-bit (length - 1); then the
@@ -245,7 +258,8 @@ static int decode_rle_v2(const uint8_t *in, uint64_t in_len, uint8_t *out,
             if (n + len > cap_values) { st = ORACLE_E_OVERFLOW; goto done; }
             st = read_packed(&r, len, w, vals);
             if (st) goto done;
-            for (k = 0; k < len; k++) put_i64(out, n + k, (uint64_t)unzigzag(vals[k]));
+            for (k = 0; k < len; k++)
+                put_elem(out, n + k, uns ? vals[k] : (uint64_t)unzigzag(vals[k]), eb);
             n += len;
         } else if (type == 2) {
             /* PATCHED_BASE: data width code and 9-bit (length - 1) as in
@@ -294,7 +308,7 @@ static int decode_rle_v2(const uint8_t *in, uint64_t in_len, uint8_t *out,
                 if (cursor >= len) { st = ORACLE_E_CORRUPT; goto done; }
                 if (w < 64) vals[cursor] |= patch << w; /* bits past 63 are dropped */
             }
-            for (k = 0; k < len; k++) put_i64(out, n + k, (uint64_t)base + vals[k]);
+            for (k = 0; k < len; k++) put_elem(out, n + k, (uint64_t)base + vals[k], eb);
             n += len;
         } else {
             /* DELTA: width code in bits 5..1 where code 0 means a fixed
@@ -302,26 +316,26 @@ static int decode_rle_v2(const uint8_t *in, uint64_t in_len, uint8_t *out,
              * base varint; then length - 2 delta magnitudes whose sign is
              * the delta base's. */
             int code, w;
-            uint64_t len, k, cur;
-            int64_t base, dbase;
+            uint64_t len, k, cur, base;
+            int64_t dbase;
             st = br_byte(&r, &b1);
             if (st) goto done;
             code = (b0 >> 1) & 31;
             w = code == 0 ? 0 : orc_decode_width(code);
             len = ((uint64_t)(b0 & 1) << 8 | b1) + 1;
-            st = br_svarint(&r, &base);
+            st = br_value_varint(&r, uns, &base); /* the delta base is always signed */
             if (st) goto done;
             st = br_svarint(&r, &dbase);
             if (st) goto done;
             if (n + len > cap_values) { st = ORACLE_E_OVERFLOW; goto done; }
             if (w == 0) {
                 for (k = 0; k < len; k++)
-                    put_i64(out, n + k, (uint64_t)base + k * (uint64_t)dbase);
+                    put_elem(out, n + k, base + k * (uint64_t)dbase, eb);
             } else {
-                put_i64(out, n, (uint64_t)base);
+                put_elem(out, n, base, eb);
                 if (len >= 2) {
-                    cur = (uint64_t)base + (uint64_t)dbase;
-                    put_i64(out, n + 1, cur);
+                    cur = base + (uint64_t)dbase;
+                    put_elem(out, n + 1, cur, eb);
                     st = read_packed(&r, len - 2, w, vals);
                     if (st) goto done;
                     for (k = 2; k < len; k++) {
@@ -329,7 +343,7 @@ static int decode_rle_v2(const uint8_t *in, uint64_t in_len, uint8_t *out,
                             cur += vals[k - 2];
                         else
                             cur -= vals[k - 2];
-                        put_i64(out, n + k, cur);
+                        put_elem(out, n + k, cur, eb);
                     }
                 }
             }
@@ -612,7 +626,7 @@ static int inflate_dynamic(bit_reader *r, out_window *o, code_set *c) {
 /* The blocks of one raw Deflate stream (RFC 1951 section 3.2.3): BFINAL,
  * BTYPE, the block; after the final block the output must be full. */
 static int decode_deflate(const uint8_t *in, uint64_t in_len, uint8_t *out,
-                          uint64_t cap, uint64_t *n_out, code_set *c) {
+                          uint64_t cap, uint64_t *n_out, code_set *c, int capacity_mode) {
     bit_reader r = {in, 8 * in_len, 0};
     out_window o = {out, cap, 0};
     int st = ORACLE_OK;
@@ -632,7 +646,8 @@ static int decode_deflate(const uint8_t *in, uint64_t in_len, uint8_t *out,
             st = ORACLE_E_CORRUPT;
         if (st) break;
         if (last) {
-            if (o.n != o.cap) st = ORACLE_E_UNDERFLOW;
+            /* With capacity_mode the output range is only an upper bound. */
+            if (o.n != o.cap && !capacity_mode) st = ORACLE_E_UNDERFLOW;
             break;
         }
     }
@@ -655,41 +670,107 @@ static int code_set_init(code_set *c) {
 static void code_set_free(code_set *c) { free(c->lit.symbol_of); }
 
 /* ------------------------------------------------------------------ */
+/* ORC byte RLE                                                          */
+/* ------------------------------------------------------------------ */
+/*
+ * A group starts with a signed header byte h.
+ *   h in [0, 127]:   a run of h + 3 copies of the next byte.
+ *   h in [-128, -1]: -h literal bytes follow.
+ * Used by ORC for byte columns and, over bit-packed booleans, for
+ * PRESENT streams.  End conditions as for the integer encodings: decode
+ * until the output is full; a run that does not fit is OVERFLOW (after its
+ * byte is read), a literal list that does not fit is OVERFLOW (before its
+ * bytes are read), input ending first is TRUNCATED, input left over is
+ * CORRUPT.
+ */
+static int decode_byte_rle(const uint8_t *in, uint64_t in_len, uint8_t *out,
+                           uint64_t cap, uint64_t *n_out) {
+    byte_reader r = {in, in_len, 0};
+    uint64_t n = 0, k;
+    int st = ORACLE_OK;
+    while (n < cap) {
+        uint8_t hb, b;
+        int8_t h;
+        st = br_byte(&r, &hb);
+        if (st) goto done;
+        h = (int8_t)hb;
+        if (h >= 0) {
+            uint64_t len = (uint64_t)h + 3;
+            st = br_byte(&r, &b);
+            if (st) goto done;
+            if (n + len > cap) { st = ORACLE_E_OVERFLOW; goto done; }
+            for (k = 0; k < len; k++) out[n++] = b;
+        } else {
+            uint64_t len = (uint64_t)(-(int)h);
+            if (n + len > cap) { st = ORACLE_E_OVERFLOW; goto done; }
+            for (k = 0; k < len; k++) {
+                st = br_byte(&r, &b);
+                if (st) goto done;
+                out[n++] = b;
+            }
+        }
+    }
+    if (r.pos != r.len) st = ORACLE_E_CORRUPT;
+done:
+    *n_out = n;
+    return st;
+}
+
+/* ------------------------------------------------------------------ */
 /* Entry points                                                         */
 /* ------------------------------------------------------------------ */
 
 /* One chunk; c holds the Huffman key table for Deflate (NULL otherwise). */
 static int decode_one_chunk(int codec, const uint8_t *in, uint64_t in_len, uint8_t *out,
-                            uint64_t out_cap, uint64_t *produced, code_set *c) {
+                            uint64_t out_cap, uint64_t *produced, code_set *c, int eb, int uns,
+                            int capacity_mode) {
     uint64_t n = 0;
     int st;
     *produced = 0;
     if (codec == ORACLE_RLE_V1 || codec == ORACLE_RLE_V2) {
-        /* Values are whole little-endian int64s starting 8-byte aligned. */
-        if (out_cap % 8 != 0 || ((uintptr_t)out & 7) != 0) return ORACLE_E_INVALID_ARGUMENT;
+        /* Values are whole little-endian integers of eb bytes, aligned. */
+        if (out_cap % (uint64_t)eb != 0 || ((uintptr_t)out % (uintptr_t)eb) != 0)
+            return ORACLE_E_INVALID_ARGUMENT;
         if (codec == ORACLE_RLE_V1)
-            st = decode_rle_v1(in, in_len, out, out_cap / 8, &n);
+            st = decode_rle_v1(in, in_len, out, out_cap / eb, &n, eb, uns);
         else
-            st = decode_rle_v2(in, in_len, out, out_cap / 8, &n);
-        *produced = n * 8;
+            st = decode_rle_v2(in, in_len, out, out_cap / eb, &n, eb, uns);
+        *produced = n * eb;
+        return st;
+    }
+    if (codec == ORACLE_BYTE_RLE) {
+        st = decode_byte_rle(in, in_len, out, out_cap, &n);
+        *produced = n;
         return st;
     }
     if (codec == ORACLE_DEFLATE && c) {
-        st = decode_deflate(in, in_len, out, out_cap, &n, c);
+        st = decode_deflate(in, in_len, out, out_cap, &n, c, capacity_mode);
         *produced = n;
         return st;
     }
     return ORACLE_E_INVALID_ARGUMENT;
 }
 
+static int valid_elem(int eb) { return eb == 1 || eb == 2 || eb == 4 || eb == 8; }
+
 int oracle_decode_chunk(int codec, const uint8_t *in, uint64_t in_len,
                         uint8_t *out, uint64_t out_cap, uint64_t *produced) {
+    return oracle_decode_chunk_ex(codec, 8, 0, 0, in, in_len, out, out_cap, produced);
+}
+
+int oracle_decode_chunk_ex(int codec, int elem_bytes, int is_unsigned, int capacity_mode,
+                           const uint8_t *in, uint64_t in_len, uint8_t *out, uint64_t out_cap,
+                           uint64_t *produced) {
     code_set c;
     int st;
     *produced = 0;
-    if (codec != ORACLE_DEFLATE) return decode_one_chunk(codec, in, in_len, out, out_cap, produced, NULL);
+    if (!valid_elem(elem_bytes)) return ORACLE_E_INVALID_ARGUMENT;
+    if (codec != ORACLE_DEFLATE)
+        return decode_one_chunk(codec, in, in_len, out, out_cap, produced, NULL, elem_bytes,
+                                is_unsigned, capacity_mode);
     if (code_set_init(&c)) return ORACLE_E_INVALID_ARGUMENT;
-    st = decode_one_chunk(codec, in, in_len, out, out_cap, produced, &c);
+    st = decode_one_chunk(codec, in, in_len, out, out_cap, produced, &c, elem_bytes, is_unsigned,
+                          capacity_mode);
     code_set_free(&c);
     return st;
 }
@@ -698,13 +779,21 @@ int oracle_decompress(int codec, const uint8_t *comp,
                       const uint64_t *chunk_offsets, uint8_t *out,
                       const uint64_t *out_offsets, uint64_t n_chunks,
                       int32_t *status) {
+    return oracle_decompress_ex(codec, 8, 0, 0, comp, chunk_offsets, out, out_offsets, n_chunks,
+                                status, NULL);
+}
+
+int oracle_decompress_ex(int codec, int elem_bytes, int is_unsigned, int capacity_mode,
+                         const uint8_t *comp, const uint64_t *chunk_offsets, uint8_t *out,
+                         const uint64_t *out_offsets, uint64_t n_chunks, int32_t *status,
+                         uint64_t *produced) {
     uint64_t i;
     code_set c;
-    if (codec < ORACLE_RLE_V1 || codec > ORACLE_DEFLATE) return -1;
+    if (codec < ORACLE_RLE_V1 || codec > ORACLE_BYTE_RLE || !valid_elem(elem_bytes)) return -1;
     if (n_chunks && (!comp || !chunk_offsets || !out || !out_offsets)) return -1;
     if (codec == ORACLE_DEFLATE && code_set_init(&c)) return -1;
     for (i = 0; i < n_chunks; i++) {
-        uint64_t produced;
+        uint64_t made = 0;
         int st;
         if (chunk_offsets[i + 1] < chunk_offsets[i] || out_offsets[i + 1] < out_offsets[i])
             st = ORACLE_E_INVALID_ARGUMENT;
@@ -712,10 +801,66 @@ int oracle_decompress(int codec, const uint8_t *comp,
             st = decode_one_chunk(codec, comp + chunk_offsets[i],
                                   chunk_offsets[i + 1] - chunk_offsets[i],
                                   out + out_offsets[i],
-                                  out_offsets[i + 1] - out_offsets[i], &produced,
-                                  codec == ORACLE_DEFLATE ? &c : NULL);
+                                  out_offsets[i + 1] - out_offsets[i], &made,
+                                  codec == ORACLE_DEFLATE ? &c : NULL, elem_bytes, is_unsigned,
+                                  capacity_mode);
         if (status) status[i] = st;
+        if (produced) produced[i] = made;
     }
     if (codec == ORACLE_DEFLATE) code_set_free(&c);
     return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* ORC compressed streams                                               */
+/* ------------------------------------------------------------------ */
+/*
+ * A compressed ORC stream is a sequence of compression chunks, each a
+ * 3-byte little-endian header (length << 1 | original) and `length` bytes:
+ * the bytes themselves if `original` is set, else the chunk compressed on
+ * its own -- for the ZLIB codec a raw Deflate stream.  Readings (the format
+ * leaves them open): every chunk but the last of a stream holds exactly
+ * block_size uncompressed bytes, as Apache ORC's writers produce them (a
+ * shorter one is UNDERFLOW, a longer one OVERFLOW); the last holds at most
+ * block_size; a header or chunk cut off by the end of the stream is
+ * TRUNCATED; more output than out_cap is OVERFLOW.  The statuses are those
+ * of the first chunk that fails.
+ */
+int oracle_orc_inflate_stream(const uint8_t *in, uint64_t in_len, uint64_t block_size,
+                              uint8_t *out, uint64_t out_cap, uint64_t *out_len) {
+    uint64_t pos = 0, n = 0;
+    code_set c;
+    int st = ORACLE_OK;
+    *out_len = 0;
+    if (block_size == 0 || block_size >= (1u << 23)) return ORACLE_E_INVALID_ARGUMENT;
+    if (code_set_init(&c)) return ORACLE_E_INVALID_ARGUMENT;
+    while (pos < in_len) {
+        uint64_t h, len, room, made = 0;
+        int last;
+        if (in_len - pos < 3) { st = ORACLE_E_TRUNCATED; break; }
+        h = (uint64_t)in[pos] | (uint64_t)in[pos + 1] << 8 | (uint64_t)in[pos + 2] << 16;
+        pos += 3;
+        len = h >> 1;
+        if (in_len - pos < len) { st = ORACLE_E_TRUNCATED; break; }
+        last = pos + len == in_len;
+        room = out_cap - n < block_size ? out_cap - n : block_size;
+        if (h & 1) {
+            /* original bytes */
+            if (len > room) { st = ORACLE_E_OVERFLOW; break; }
+            memcpy(out + n, in + pos, len);
+            made = len;
+        } else {
+            st = decode_deflate(in + pos, len, out + n, room, &made, &c, 1);
+            if (st) break;
+        }
+        if (!last && made != block_size) {
+            st = made < block_size ? ORACLE_E_UNDERFLOW : ORACLE_E_OVERFLOW;
+            break;
+        }
+        n += made;
+        pos += len;
+    }
+    code_set_free(&c);
+    *out_len = n;
+    return st;
 }

@@ -10,7 +10,9 @@
  * Deflate, each chunk compressed independently (Section II-B).  The paper
  * names the formats but does not define their bits; the bit layouts
  * followed here are the Apache ORC integer run-length encodings and
- * RFC 1951.  All RLE columns are signed 64-bit little-endian integers.
+ * RFC 1951.  RLE columns are signed 64-bit little-endian integers unless
+ * the _ex entry points say otherwise; ORC's byte RLE and its compressed
+ * stream framing (the read path around the decoders) are here too.
  */
 #ifndef CODAG_ORACLE_H
 #define CODAG_ORACLE_H
@@ -25,6 +27,7 @@ extern "C" {
 #define ORACLE_RLE_V1 1
 #define ORACLE_RLE_V2 2
 #define ORACLE_DEFLATE 3
+#define ORACLE_BYTE_RLE 4
 
 /* Per-chunk status values (same numbering as the public library). */
 #define ORACLE_OK 0
@@ -52,6 +55,33 @@ int oracle_decompress(int codec, const uint8_t *comp,
                       const uint64_t *chunk_offsets, uint8_t *out,
                       const uint64_t *out_offsets, uint64_t n_chunks,
                       int32_t *status);
+
+/*
+ * As above, with the element type of the RLE codecs -- elem_bytes 1, 2, 4
+ * or 8 (the low bytes of each decoded value, little-endian) and is_unsigned
+ * (values read without zigzag, as ORC writes unsigned streams; the DELTA
+ * delta base stays signed) -- and, with capacity_mode, Deflate output
+ * ranges as upper bounds (status OK when the final block ends inside the
+ * range).  produced[i] (may be NULL) receives chunk i's output bytes.
+ * Codec ORACLE_BYTE_RLE decodes ORC byte RLE (elem_bytes and is_unsigned
+ * ignored).
+ */
+int oracle_decode_chunk_ex(int codec, int elem_bytes, int is_unsigned, int capacity_mode,
+                           const uint8_t *in, uint64_t in_len, uint8_t *out, uint64_t out_cap,
+                           uint64_t *produced);
+int oracle_decompress_ex(int codec, int elem_bytes, int is_unsigned, int capacity_mode,
+                         const uint8_t *comp, const uint64_t *chunk_offsets, uint8_t *out,
+                         const uint64_t *out_offsets, uint64_t n_chunks, int32_t *status,
+                         uint64_t *produced);
+
+/*
+ * One compressed ORC stream (ZLIB codec) into out[0..out_cap): its
+ * compression chunks -- 3-byte header (length << 1 | original), then the
+ * original bytes or a raw Deflate stream -- in order.  *out_len receives the
+ * bytes produced.  Returns a status (see oracle.c for the readings).
+ */
+int oracle_orc_inflate_stream(const uint8_t *in, uint64_t in_len, uint64_t block_size,
+                              uint8_t *out, uint64_t out_cap, uint64_t *out_len);
 
 #ifdef __cplusplus
 }

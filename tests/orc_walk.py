@@ -135,3 +135,59 @@ def rle_v2_width_codes(stream: bytes):
     if i != len(stream):
         raise ValueError("runs do not end at the end of the stream")
     return codes
+
+
+def _unframe_meta(buf: bytes, compressed: bool) -> bytes:
+    """Metadata sections (footer, stripe footers) of a ZLIB-compressed file:
+    the compression chunks inflated with Python's zlib.  Test plumbing only
+    (the data streams go through the oracle and the GPU path)."""
+    if not compressed:
+        return buf
+    import zlib
+    out, pos = bytearray(), 0
+    while pos < len(buf):
+        h = buf[pos] | buf[pos + 1] << 8 | buf[pos + 2] << 16
+        pos += 3
+        n = h >> 1
+        chunk = buf[pos:pos + n]
+        pos += n
+        out += chunk if h & 1 else zlib.decompress(chunk, -15)
+    return bytes(out)
+
+
+# ORC stream kinds (Stream.Kind) and column encodings (ColumnEncoding.Kind).
+PRESENT, DATA, LENGTH = 0, 1, 2
+DIRECT, DIRECT_V2 = 0, 2
+
+
+def file_streams(path: str):
+    """The raw (still framed, if compressed) streams of every stripe:
+    {"compression": 0 none / 1 zlib, "block_size": int, "stripes": [
+    {"rows": n, "streams": {(column, kind): bytes}, "encodings": [kind per column]}]}."""
+    data = open(path, "rb").read()
+    ps_len = data[-1]
+    ps = dict((num, v) for num, _, v in _fields(data[-1 - ps_len:-1]))
+    footer_len, compression, block = ps[1], ps.get(2, 0), ps.get(3, 256 * 1024)
+    if compression not in (0, 1):
+        raise ValueError("only uncompressed and ZLIB files")
+    footer = _unframe_meta(data[-1 - ps_len - footer_len:-1 - ps_len], compression == 1)
+    stripes = []
+    for num, _, v in _fields(footer):
+        if num != 3:
+            continue
+        info = {n: val for n, _, val in _fields(v)}
+        offset, index_len, data_len, sf_len, rows = info[1], info.get(2, 0), info[3], info[4], info.get(5, 0)
+        sf = _unframe_meta(data[offset + index_len + data_len:offset + index_len + data_len + sf_len],
+                           compression == 1)
+        streams, encodings, pos = {}, [], offset
+        for n2, _, v2 in _fields(sf):
+            if n2 == 1:
+                s = {n: val for n, _, val in _fields(v2)}
+                kind, col, length = s.get(1, 0), s.get(2, 0), s.get(3, 0)
+                if pos >= offset + index_len:
+                    streams[(col, kind)] = data[pos:pos + length]
+                pos += length
+            elif n2 == 2:
+                encodings.append({n: val for n, _, val in _fields(v2)}.get(1, 0))
+        stripes.append({"rows": rows, "streams": streams, "encodings": encodings})
+    return {"compression": compression, "block_size": block, "stripes": stripes}
