@@ -26,9 +26,13 @@ extern "C" {
 
 /* Codecs. */
 enum {
-    CODAG_RLE_V1 = 1,  /* ORC integer RLE v1, signed int64 (zigzag varints) */
-    CODAG_RLE_V2 = 2,  /* ORC integer RLE v2, signed int64 */
-    CODAG_DEFLATE = 3  /* raw RFC 1951 stream per chunk */
+    CODAG_RLE_V1 = 1,   /* ORC integer RLE v1, signed int64 (zigzag varints) unless codag_opts
+                           names another element type */
+    CODAG_RLE_V2 = 2,   /* ORC integer RLE v2, likewise */
+    CODAG_DEFLATE = 3,  /* raw RFC 1951 stream per chunk */
+    CODAG_BYTE_RLE = 4  /* ORC byte RLE (byte columns, PRESENT bitmaps): a header 0..127 is a
+                           run of header + 3 copies of the next byte, -1..-128 is followed by
+                           -header literal bytes; output is bytes */
 };
 
 /* Status codes: return values and per-chunk statuses. */
@@ -90,6 +94,17 @@ enum {
  *                       write it.  RLE v1 only.
  *                     Other codecs, or a variant a codec lacks, return
  *                     CODAG_E_INVALID_ARGUMENT.
+ *   elem_bytes        RLE codecs: bytes per output value, 1, 2, 4 or 8 (0 =
+ *                     8).  Each value is stored as the low bytes of its
+ *                     64-bit decoded value, little-endian (how an ORC
+ *                     short/int column holds it); output ranges must be a
+ *                     multiple of elem_bytes and aligned to it.
+ *   unsigned_values   RLE codecs: 1 = the stream is unsigned (no zigzag;
+ *                     ORC writes string lengths and other unsigned streams
+ *                     so; the RLE v2 DELTA delta base stays signed).
+ *                     Element types other than signed 8-byte values use the
+ *                     one-wave-per-chunk decoder (group_parallel 2 and the
+ *                     variants return CODAG_E_INVALID_ARGUMENT).
  */
 enum {
     CODAG_VARIANT_DEFAULT = 0,
@@ -104,7 +119,9 @@ typedef struct codag_opts {
     int history_kib;
     int group_parallel;
     int variant;
-    int reserved[5];
+    int elem_bytes;
+    int unsigned_values;
+    int reserved[3];
 } codag_opts;
 
 /*
@@ -169,6 +186,34 @@ int codag_decompress_ex(int codec, const uint8_t *comp_buf, const uint64_t *chun
 int codag_decompress_noalloc(int codec, const uint8_t *comp_buf, const uint64_t *chunk_offsets,
                              uint8_t *out_buf, const uint64_t *out_offsets, uint64_t n_chunks,
                              void *stream, int32_t *chunk_status, const struct codag_opts *opts);
+
+/*
+ * The read path around the decoders (CODAG Section I places decoding inside
+ * ORC/Parquet reads): one compressed ORC stream, ZLIB codec, decompressed
+ * into out[0 .. out_cap) on the device.  The stream is a sequence of
+ * compression chunks, each a 3-byte little-endian header (length << 1 |
+ * original) and `length` bytes -- the bytes themselves if `original`, else
+ * a raw Deflate stream.  Every chunk but the last holds exactly block_size
+ * uncompressed bytes (as Apache ORC's writers produce them; a shorter one
+ * is CODAG_E_UNDERFLOW, a longer one CODAG_E_OVERFLOW), the last at most
+ * block_size; a header or chunk cut off by the end of the stream is
+ * CODAG_E_TRUNCATED; output past out_cap is CODAG_E_OVERFLOW.  The chunks
+ * are located by one wave and decoded in parallel, one wave per chunk, each
+ * straight into its place in out.
+ *   framed       device, framed_len bytes (the stream as stored in the file).
+ *   out_len      device uint64: bytes produced (valid when *status is OK).
+ *   status       device int32: CODAG_OK or the status of the first chunk
+ *                that failed, in stream order.
+ * block_size must be 1..2^23 - 1 (the file's compressionBlockSize).  Takes a
+ * workspace of 16 bytes per possible chunk (out_cap / block_size + 2) from
+ * the stream-ordered allocator.  Enqueued on `stream`; returns
+ * CODAG_E_INVALID_ARGUMENT for bad arguments, CODAG_E_HIP on a launch
+ * failure.  The decompressed stream is then decoded with codag_decompress
+ * (for example as RLE v2, or byte RLE for a PRESENT stream).
+ */
+int codag_orc_inflate_stream(const uint8_t *framed, uint64_t framed_len, uint32_t block_size,
+                             uint8_t *out, uint64_t out_cap, uint64_t *out_len, int32_t *status,
+                             void *stream);
 
 /*
  * Return the status of the lowest-indexed chunk that failed in any call on

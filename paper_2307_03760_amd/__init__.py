@@ -18,6 +18,7 @@ RLE_V1, RLE_V2, DEFLATE = 1, 2, 3
 ORDER_INDEX, ORDER_GIVEN, ORDER_LEARNED = 0, 1, 2
 SCHED_FEATURES, SCHED_PARAMS, SCHED_NORM = 16, 5313, 34
 OK = 0
+RLE_V1, RLE_V2, DEFLATE, BYTE_RLE = 1, 2, 3, 4
 VARIANT_DEFAULT, VARIANT_LEADER_LANE, VARIANT_PREFETCH_WAVE, VARIANT_BLOCK_LEADER = 0, 1, 2, 3
 E_INVALID_ARGUMENT, E_HIP, E_CORRUPT, E_TRUNCATED, E_OVERFLOW, E_UNDERFLOW = -1, -2, -3, -4, -5, -6
 
@@ -35,7 +36,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_int), ("lit_table_bits", ctypes.c_int),
                 ("chunk_ticks", ctypes.c_void_p), ("history_kib", ctypes.c_int),
                 ("group_parallel", ctypes.c_int), ("variant", ctypes.c_int),
-                ("reserved", ctypes.c_int * 5)]
+                ("elem_bytes", ctypes.c_int), ("unsigned_values", ctypes.c_int),
+                ("reserved", ctypes.c_int * 3)]
 
 
 class BatchOpts(ctypes.Structure):
@@ -60,6 +62,8 @@ def lib():
             L.codag_decompress_ex.restype = i32
             L.codag_decompress_noalloc.argtypes = [i32, vp, vp, vp, vp, u64, vp, vp, ctypes.POINTER(Opts)]
             L.codag_decompress_noalloc.restype = i32
+            L.codag_orc_inflate_stream.argtypes = [vp, u64, ctypes.c_uint32, vp, u64, vp, vp, vp]
+            L.codag_orc_inflate_stream.restype = i32
             L.codag_get_error.argtypes = [vp, ctypes.POINTER(u64)]
             L.codag_get_error.restype = i32
             L.codag_status_string.argtypes = [i32]
@@ -122,7 +126,8 @@ def _check_dev(t, name, dtype=None, n=None):
 
 def decompress(codec: int, comp, chunk_offsets, out, out_offsets, *, status=None,
                waves_per_block: int = 0, lit_table_bits: int = 0, history_kib: int = 0,
-               group_parallel: int = 0, chunk_ticks=None, variant: int = 0, stream=None) -> None:
+               group_parallel: int = 0, chunk_ticks=None, variant: int = 0, elem_bytes: int = 0,
+               unsigned_values: bool = False, stream=None) -> None:
     """Enqueue codag_decompress_ex on `stream` (default: torch's current stream).
 
     comp: uint8 device tensor; chunk_offsets/out_offsets: int64 device tensors of
@@ -131,11 +136,12 @@ def decompress(codec: int, comp, chunk_offsets, out, out_offsets, *, status=None
     """
     _decompress("codag_decompress_ex", codec, comp, chunk_offsets, out, out_offsets, status,
                 waves_per_block, lit_table_bits, history_kib, group_parallel, chunk_ticks, variant,
-                stream)
+                elem_bytes, unsigned_values, stream)
 
 
 def _decompress(entry, codec, comp, chunk_offsets, out, out_offsets, status, waves_per_block,
-                lit_table_bits, history_kib, group_parallel, chunk_ticks, variant, stream):
+                lit_table_bits, history_kib, group_parallel, chunk_ticks, variant, elem_bytes,
+                unsigned_values, stream):
     import torch
     n = chunk_offsets.numel() - 1
     if n < 0 or out_offsets.numel() != n + 1:
@@ -148,7 +154,7 @@ def _decompress(entry, codec, comp, chunk_offsets, out, out_offsets, status, wav
     s = _check_dev(status, "status", (torch.int32,), n)
     t = _check_dev(chunk_ticks, "chunk_ticks", (torch.int64,), n)
     opts = Opts(waves_per_block, lit_table_bits, t, history_kib, group_parallel, variant,
-                (ctypes.c_int * 5)())
+                elem_bytes, int(unsigned_values), (ctypes.c_int * 3)())
     rc = getattr(lib(), entry)(int(codec), a, b, c, d, n, _stream_handle(stream), s,
                                ctypes.byref(opts))
     if rc != OK:
@@ -158,13 +164,28 @@ def _decompress(entry, codec, comp, chunk_offsets, out, out_offsets, status, wav
 def decompress_noalloc(codec: int, comp, chunk_offsets, out, out_offsets, *, status=None,
                        waves_per_block: int = 0, lit_table_bits: int = 0, history_kib: int = 0,
                        group_parallel: int = 0, chunk_ticks=None, variant: int = 0,
-                       stream=None) -> None:
+                       elem_bytes: int = 0, unsigned_values: bool = False, stream=None) -> None:
     """Enqueue codag_decompress_noalloc (arguments as decompress()): the same
     decode with every workspace in the library's static per-device scratch
     array; calls that overlap in time on one device must not be made."""
     _decompress("codag_decompress_noalloc", codec, comp, chunk_offsets, out, out_offsets, status,
                 waves_per_block, lit_table_bits, history_kib, group_parallel, chunk_ticks, variant,
-                stream)
+                elem_bytes, unsigned_values, stream)
+
+
+def orc_inflate_stream(framed, block_size: int, out, out_len, status, *, stream=None) -> None:
+    """Enqueue codag_orc_inflate_stream: framed (uint8 device tensor, the
+    compressed ORC stream), out (uint8 device tensor, capacity out.numel()),
+    out_len (int64 device tensor of 1), status (int32 device tensor of 1)."""
+    import torch
+    a = _check_dev(framed, "framed", (torch.uint8,))
+    b = _check_dev(out, "out", (torch.uint8,))
+    c = _check_dev(out_len, "out_len", (torch.int64,), 1)
+    d = _check_dev(status, "status", (torch.int32,), 1)
+    rc = lib().codag_orc_inflate_stream(a, framed.numel(), int(block_size), b, out.numel(), c, d,
+                                        _stream_handle(stream))
+    if rc != OK:
+        raise CodagError(rc, "codag_orc_inflate_stream")
 
 
 def get_error(stream=None):

@@ -7,7 +7,7 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("codag.hip", "batch.hip", "sched.hip", "split.hip", "ablation.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("codag.hip", "batch.hip", "sched.hip", "split.hip", "ablation.hip", "typed.hip")]
 OUT = os.path.join(HERE, "libcodag.so")
 
 HIPCC_FLAGS = [

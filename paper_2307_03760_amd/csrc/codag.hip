@@ -145,8 +145,16 @@ namespace {
 int decompress(int codec, const uint8_t *comp_buf, const uint64_t *chunk_offsets, uint8_t *out_buf,
                const uint64_t *out_offsets, uint64_t n_chunks, void *stream, int32_t *chunk_status,
                const codag_opts *opts, bool noalloc) {
-    if (codec != CODAG_RLE_V1 && codec != CODAG_RLE_V2 && codec != CODAG_DEFLATE)
+    if (codec != CODAG_RLE_V1 && codec != CODAG_RLE_V2 && codec != CODAG_DEFLATE &&
+        codec != CODAG_BYTE_RLE)
         return CODAG_E_INVALID_ARGUMENT;
+    const int eb = opts && opts->elem_bytes ? opts->elem_bytes : 8;
+    const int uns = opts ? opts->unsigned_values : 0;
+    if ((eb != 1 && eb != 2 && eb != 4 && eb != 8) || (uns != 0 && uns != 1)) return CODAG_E_INVALID_ARGUMENT;
+    // Byte RLE, and RLE element types other than signed 8-byte values, take
+    // the one-wave-per-chunk typed decoder.
+    const bool typed = codec == CODAG_BYTE_RLE || (codec != CODAG_DEFLATE && (eb != 8 || uns));
+    if (typed && opts && (opts->variant || opts->group_parallel == 2)) return CODAG_E_INVALID_ARGUMENT;
     if (n_chunks == 0) return CODAG_OK;
     if (!comp_buf || !chunk_offsets || !out_buf || !out_offsets) return CODAG_E_INVALID_ARGUMENT;
     if (n_chunks >= (1ull << 32) - 64) return CODAG_E_INVALID_ARGUMENT;
@@ -171,6 +179,9 @@ int decompress(int codec, const uint8_t *comp_buf, const uint64_t *chunk_offsets
     if (variant)
         return launch_variant(variant, codec, comp_buf, chunk_offsets, out_buf, out_offsets,
                               (uint32_t)n_chunks, chunk_status, ds->err, s);
+    if (typed)
+        return launch_typed(codec, eb, uns != 0, comp_buf, chunk_offsets, out_buf, out_offsets,
+                            (uint32_t)n_chunks, chunk_status, ds->err, ticks, s);
     switch (codec) {
         case CODAG_RLE_V1: {
             const int gp = opts ? opts->group_parallel : 0;

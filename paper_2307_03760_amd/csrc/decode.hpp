@@ -23,8 +23,10 @@ __device__ __forceinline__ uint64_t error_key(uint64_t chunk, int st) {
     return (chunk << 4) | (uint64_t)(uint32_t)(-st);
 }
 
-// Decodes chunk c with the calling wave; returns its status.
-template <int Codec, int TB, uint32_t H>
+// Decodes chunk c with the calling wave; returns its status.  E is the
+// element type of the RLE codecs (int64 unless a typed launch says
+// otherwise).
+template <int Codec, int TB, uint32_t H, class E = I64>
 __device__ __forceinline__ int decode_one(const uint8_t *comp, const uint64_t *coff, uint8_t *out,
                                           const uint64_t *ooff, uint32_t c, uint32_t *ring,
                                           uint32_t *land, WaveScratch<Codec, TB, H> *scratch) {
@@ -39,14 +41,18 @@ __device__ __forceinline__ int decode_one(const uint8_t *comp, const uint64_t *c
         if (in_len >= (1u << 28)) return CODAG_E_INVALID_ARGUMENT;  // bit counts fit 31 bits
         in.init(comp + i0, in_len, ring, land);
         st = decode_deflate<TB, H>(in, dst, out_len, &scratch->t);
-    } else {
-        if ((out_len & 7) || (reinterpret_cast<uintptr_t>(dst) & 7)) return CODAG_E_INVALID_ARGUMENT;
+    } else if constexpr (Codec == CODAG_BYTE_RLE) {
         in.init(comp + i0, in_len, ring, land);
-        uint64_t *dst64 = reinterpret_cast<uint64_t *>(dst);
+        st = decode_byte_rle(in, dst, out_len);
+    } else {
+        constexpr uint32_t B = E::kBytes;
+        if ((out_len % B) || (reinterpret_cast<uintptr_t>(dst) % B)) return CODAG_E_INVALID_ARGUMENT;
+        in.init(comp + i0, in_len, ring, land);
+        typename E::T *dstv = reinterpret_cast<typename E::T *>(dst);
         if constexpr (Codec == CODAG_RLE_V1)
-            st = decode_rle_v1(in, dst64, out_len / 8);
+            st = decode_rle_v1<E>(in, dstv, out_len / B);
         else
-            st = decode_rle_v2(in, dst64, out_len / 8);
+            st = decode_rle_v2<E>(in, dstv, out_len / B);
     }
     // The landing buffer may still have a fetch in flight: let it land before
     // the wave moves on or exits.

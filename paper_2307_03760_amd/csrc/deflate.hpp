@@ -798,9 +798,11 @@ __device__ __forceinline__ int inflate_leader(Ring &in, BitIn &bi, WindowOut<H> 
 // against, Section V-E).
 enum : int { kAllLanes = 0, kLeaderLane = 1 };
 
+// With `made` non-null the output range is a capacity: a final block that
+// ends inside it is OK and *made receives the bytes produced.
 template <int TB, uint32_t H, int MODE = kAllLanes, class Ring>
 __device__ __forceinline__ int decode_deflate(Ring &in, uint8_t *out, uint32_t cap,
-                                              DeflateLds<TB, H> *lds) {
+                                              DeflateLds<TB, H> *lds, uint32_t *made = nullptr) {
     const uint32_t l = lane();
     BitIn bi;
     bi.seek(in, in.skip);
@@ -891,6 +893,10 @@ __device__ __forceinline__ int decode_deflate(Ring &in, uint8_t *out, uint32_t c
     }
     o.finish();
     if (st) return st;
+    if (made) {
+        *made = o.pos;
+        return CODAG_OK;
+    }
     return o.pos == cap ? CODAG_OK : CODAG_E_UNDERFLOW;
 }
 

@@ -52,6 +52,12 @@ int launch_variant(int variant, int codec, const uint8_t *comp, const uint64_t *
                    const uint64_t *ooff, uint32_t n, int32_t *status, unsigned long long *err,
                    hipStream_t s);
 
+// Byte RLE and RLE element types other than signed 8-byte values (one wave
+// per chunk), on stream s.
+int launch_typed(int codec, int elem_bytes, bool is_unsigned, const uint8_t *comp, const uint64_t *coff,
+                 uint8_t *out, const uint64_t *ooff, uint32_t n, int32_t *status,
+                 unsigned long long *err, uint64_t *ticks, hipStream_t s);
+
 // Arguments of one batched launch (a captured graph is reused while they
 // stay the same).
 struct BatchArgs {

@@ -9,6 +9,8 @@
 // consecutive int64 values with one instruction.
 #pragma once
 
+#include <type_traits>
+
 #include "../../include/codag.h"
 #include "stream.hpp"
 
@@ -27,6 +29,22 @@ __device__ __forceinline__ uint64_t pack7(uint64_t x) {
 __device__ __forceinline__ uint64_t low_bytes(uint64_t x, uint32_t nb) {
     return nb >= 8 ? x : x & ((1ull << (8 * nb)) - 1);
 }
+
+// Element type of an integer column: B-byte little-endian values (the low
+// bytes of each decoded 64-bit value, which is how a narrower column holds
+// it) and SIGNED values zigzag-coded, unsigned ones not (ORC writes
+// unsigned streams, such as string lengths, without zigzag).
+template <int B, bool SIGNED>
+struct Elem {
+    static constexpr int kBytes = B;
+    static constexpr bool kSigned = SIGNED;
+    using T = typename std::conditional<
+        B == 1, uint8_t,
+        typename std::conditional<B == 2, uint16_t,
+                                  typename std::conditional<B == 4, uint32_t, uint64_t>::type>::type>::type;
+    __device__ static __forceinline__ uint64_t val(uint64_t z) { return SIGNED ? unzigzag(z) : z; }
+};
+using I64 = Elem<8, true>;
 
 // An unsigned base-128 varint from its bytes: x = the first eight, y = the
 // next two (little-endian).  Returns its length in bytes (9 or 10 for the
@@ -74,9 +92,9 @@ __device__ __forceinline__ uint32_t terminators4(uint32_t w) {
 // the last terminator of the lanes below, and then every lane decodes, from
 // its registers, the varints whose terminators it holds and stores them at
 // their index -- no compaction through LDS.
-template <class Ring>
+template <class E = I64, class Ring>
 __device__ __forceinline__ int rle_literal_list(Ring &in, uint32_t &pos, uint32_t end,
-                                                uint32_t count, uint64_t *out) {
+                                                uint32_t count, typename E::T *out) {
     const uint32_t l = lane();
     uint32_t done = 0;
     while (done < count) {
@@ -127,7 +145,7 @@ __device__ __forceinline__ int rle_literal_list(Ring &in, uint32_t &pos, uint32_
                     uint64_t z = pack7(low_bytes(x, nb));
                     if (nb > 8) z |= (uint64_t)(y & 0x7f) << 56;
                     if (nb > 9) z |= (uint64_t)(b9 & 1) << 63;
-                    if (st == CODAG_OK) out[done + g] = unzigzag(z);
+                    if (st == CODAG_OK) out[done + g] = (typename E::T)E::val(z);
                 }
                 if (g == use - 1) stop = e + 1;
                 s = e + 1;
@@ -150,8 +168,8 @@ __device__ __forceinline__ int rle_literal_list(Ring &in, uint32_t &pos, uint32_
 // 0..127 = length - 3, a signed delta byte, a zigzag varint base.  Literal
 // lists: header -1..-128 = -count, then count zigzag varints.  One 16-byte
 // read gives a run's header, delta and base together.  Advances pos and n.
-template <class Ring>
-__device__ __forceinline__ int rle_v1_group(Ring &in, uint32_t &pos, uint32_t end, uint64_t *out,
+template <class E = I64, class Ring>
+__device__ __forceinline__ int rle_v1_group(Ring &in, uint32_t &pos, uint32_t end, typename E::T *out,
                                             uint32_t &n, uint32_t cap) {
     if (pos >= end) return CODAG_E_TRUNCATED;
     in.ensure(pos + 24);
@@ -170,27 +188,27 @@ __device__ __forceinline__ int rle_v1_group(Ring &in, uint32_t &pos, uint32_t en
         if (pos + 2 + nb > end) return CODAG_E_TRUNCATED;
         pos += 2 + nb;
         if (n + len > cap) return CODAG_E_OVERFLOW;
-        uint64_t base = unzigzag(z);
+        uint64_t base = E::val(z);
         for (uint32_t i = lane(); i < len; i += kWave)
-            out[n + i] = base + (uint64_t)(int64_t)((int32_t)i * delta);
+            out[n + i] = (typename E::T)(base + (uint64_t)(int64_t)((int32_t)i * delta));
         n += len;
         return CODAG_OK;
     }
     uint32_t len = (uint32_t)(-h);
     pos += 1;
     if (n + len > cap) return CODAG_E_OVERFLOW;
-    int st = rle_literal_list(in, pos, end, len, out + n);
+    int st = rle_literal_list<E>(in, pos, end, len, out + n);
     if (st) return st;
     n += len;
     return CODAG_OK;
 }
 
-template <class Ring>
-__device__ __forceinline__ int decode_rle_v1(Ring &in, uint64_t *out, uint32_t cap) {
+template <class E = I64, class Ring>
+__device__ __forceinline__ int decode_rle_v1(Ring &in, typename E::T *out, uint32_t cap) {
     uint32_t pos = in.skip, end = in.gend;
     uint32_t n = 0;
     while (n < cap) {
-        int st = rle_v1_group(in, pos, end, out, n, cap);
+        int st = rle_v1_group<E>(in, pos, end, out, n, cap);
         if (st) return st;
     }
     return pos == end ? CODAG_OK : CODAG_E_CORRUPT;
@@ -258,8 +276,9 @@ __device__ __forceinline__ void ensure_packed_batch(InRing &in, uint32_t sec, ui
 // SHORT_REPEAT, at the end of input or when the output is full, leaving pos
 // at the next unread header; when that header lies in the window, its first
 // eight bytes are returned in x (next = true).
+template <class E = I64>
 __device__ __forceinline__ int rle_v2_short_repeats(InRing &in, uint32_t &pos, uint32_t end,
-                                                    uint64_t *out, uint32_t &n, uint32_t cap,
+                                                    typename E::T *out, uint32_t &n, uint32_t cap,
                                                     uint64_t &x, bool &next) {
     const uint32_t l = lane();
     for (;;) {
@@ -269,7 +288,7 @@ __device__ __forceinline__ int rle_v2_short_repeats(InRing &in, uint32_t &pos, u
         const uint32_t h = (uint32_t)(lo & 0xff);
         const uint32_t w = ((h >> 3) & 7) + 1;
         const uint64_t vbytes = (lo >> 8) | (hi << 56);
-        const uint64_t v = unzigzag(__builtin_bswap64(vbytes) >> (64 - 8 * w));
+        const uint64_t v = E::val(__builtin_bswap64(vbytes) >> (64 - 8 * w));
         // Each lane's run, if one starts there: where the next would start
         // (below 128), or 128 + lane where the chain must stop (not a
         // SHORT_REPEAT header, or the value past the end of the input).  The
@@ -308,11 +327,15 @@ __device__ __forceinline__ int rle_v2_short_repeats(InRing &in, uint32_t &pos, u
         if (mine && l < lim) {
             // Two values per store (8-byte aligned 16-byte stores), the odd
             // last one alone.
-            typedef uint64_t u64x2 __attribute__((ext_vector_type(2), aligned(8)));
-            const u64x2 vv = {v, v};
-            for (uint32_t j = 0; j < 10; j += 2)
-                if (j + 1 < c) *reinterpret_cast<u64x2 *>(out + at + j) = vv;
-            if (c & 1) out[at + c - 1] = v;
+            if constexpr (E::kBytes == 8) {
+                typedef uint64_t u64x2 __attribute__((ext_vector_type(2), aligned(8)));
+                const u64x2 vv = {v, v};
+                for (uint32_t j = 0; j < 10; j += 2)
+                    if (j + 1 < c) *reinterpret_cast<u64x2 *>(out + at + j) = vv;
+                if (c & 1) out[at + c - 1] = v;
+            } else {
+                for (uint32_t j = 0; j < c; j++) out[at + j] = (typename E::T)v;
+            }
         }
         if (fo < ff) {
             n = uni(readlane(at, fo));
@@ -349,8 +372,10 @@ __device__ __forceinline__ int rle_v2_short_repeats(InRing &in, uint32_t &pos, u
 // Runs from byte position pos, their first value being value n of the
 // chunk, until value cap.  On an error, n is the first value of the run that
 // failed.
+template <class E = I64>
 __device__ __forceinline__ int decode_rle_v2_runs(InRing &in, uint32_t &pos, uint32_t end,
-                                                  uint64_t *out, uint32_t &n, uint32_t cap) {
+                                                  typename E::T *out, uint32_t &n, uint32_t cap) {
+    using T = typename E::T;
     const uint32_t l = lane();
     uint64_t x = 0;     // the header's first eight bytes
     bool have = false;  // x already read (handed back by a SHORT_REPEAT stretch)
@@ -362,7 +387,7 @@ __device__ __forceinline__ int decode_rle_v2_runs(InRing &in, uint32_t &pos, uin
         uint32_t b0 = (uint32_t)(x & 0xff), type = b0 >> 6;
         if (type == 0) {
             // SHORT_REPEAT: byte width and count in the header, then the value.
-            int st = rle_v2_short_repeats(in, pos, end, out, n, cap, x, have);
+            int st = rle_v2_short_repeats<E>(in, pos, end, out, n, cap, x, have);
             if (st) return st;
             continue;
         }
@@ -383,13 +408,13 @@ __device__ __forceinline__ int decode_rle_v2_runs(InRing &in, uint32_t &pos, uin
 #pragma unroll
                     for (uint32_t b = 0; b < 8; b++) {
                         uint32_t i = kWave * b + l;
-                        if (i < len) out[n + i] = unzigzag(packed_value32(in, sec, i, w));
+                        if (i < len) out[n + i] = (T)E::val(packed_value32(in, sec, i, w));
                     }
                 } else {
 #pragma unroll
                     for (uint32_t b = 0; b < 8; b++) {
                         uint32_t i = kWave * b + l;
-                        if (i < len) out[n + i] = unzigzag(packed_value(in, sec, i, w));
+                        if (i < len) out[n + i] = (T)E::val(packed_value(in, sec, i, w));
                     }
                 }
             } else if (w <= 32) {
@@ -399,8 +424,8 @@ __device__ __forceinline__ int decode_rle_v2_runs(InRing &in, uint32_t &pos, uin
                     const uint32_t i = i0 + l, j = i + kWave;
                     const uint32_t a = i < len ? packed_value32(in, sec, i, w) : 0;
                     const uint32_t b = j < len ? packed_value32(in, sec, j, w) : 0;
-                    if (i < len) out[n + i] = unzigzag(a);
-                    if (j < len) out[n + j] = unzigzag(b);
+                    if (i < len) out[n + i] = (T)E::val(a);
+                    if (j < len) out[n + j] = (T)E::val(b);
                 }
             } else if (w <= 56) {
                 // Two batches per ring check (at most 896 bytes together).
@@ -409,14 +434,14 @@ __device__ __forceinline__ int decode_rle_v2_runs(InRing &in, uint32_t &pos, uin
                     const uint32_t i = i0 + l, j = i + kWave;
                     const uint64_t a = i < len ? packed_value(in, sec, i, w) : 0;
                     const uint64_t b = j < len ? packed_value(in, sec, j, w) : 0;
-                    if (i < len) out[n + i] = unzigzag(a);
-                    if (j < len) out[n + j] = unzigzag(b);
+                    if (i < len) out[n + i] = (T)E::val(a);
+                    if (j < len) out[n + j] = (T)E::val(b);
                 }
             } else {
                 for (uint32_t i0 = 0; i0 < len; i0 += kWave) {
                     ensure_packed_batch(in, sec, i0, w);
                     uint32_t i = i0 + l;
-                    if (i < len) out[n + i] = unzigzag(packed_value(in, sec, i, w));
+                    if (i < len) out[n + i] = (T)E::val(packed_value(in, sec, i, w));
                 }
             }
             pos = sec + nbytes;
@@ -501,7 +526,7 @@ __device__ __forceinline__ int decode_rle_v2_runs(InRing &in, uint32_t &pos, uin
                         if (i == pj) v |= pt;
                         jp++;
                     }
-                    if (i < len) out[n + i] = base + v;
+                    if (i < len) out[n + i] = (T)(base + v);
                 }
                 pos = psec + pbytes;
                 n += len;
@@ -518,7 +543,7 @@ __device__ __forceinline__ int decode_rle_v2_runs(InRing &in, uint32_t &pos, uin
                     if (i == pj) v |= pt;
                     jp++;
                 }
-                if (i < len) out[n + i] = base + v;
+                if (i < len) out[n + i] = (T)(base + v);
             }
             pos = psec + pbytes;
             n += len;
@@ -559,13 +584,13 @@ __device__ __forceinline__ int decode_rle_v2_runs(InRing &in, uint32_t &pos, uin
                 p += nb2;
             }
             if (n + len > cap) return CODAG_E_OVERFLOW;
-            uint64_t base = unzigzag(zb), dbase = unzigzag(zd);
+            uint64_t base = E::val(zb), dbase = unzigzag(zd);  // the delta base is always signed
             if (w == 0) {
-                for (uint32_t i = l; i < len; i += kWave) out[n + i] = base + (uint64_t)i * dbase;
+                for (uint32_t i = l; i < len; i += kWave) out[n + i] = (T)(base + (uint64_t)i * dbase);
                 pos = p;
             } else {
-                if (l == 0) out[n] = base;
-                if (l == 1 && len >= 2) out[n + 1] = base + dbase;
+                if (l == 0) out[n] = (T)base;
+                if (l == 1 && len >= 2) out[n + 1] = (T)(base + dbase);
                 uint32_t nd = len >= 2 ? len - 2 : 0, nbytes = (nd * w + 7) >> 3;
                 if (p + nbytes > end) return CODAG_E_TRUNCATED;
                 bool neg = (uint32_t)(dbase >> 63) != 0;
@@ -582,7 +607,7 @@ __device__ __forceinline__ int decode_rle_v2_runs(InRing &in, uint32_t &pos, uin
                         const uint32_t d = i < nd ? packed_value32(in, p, i, w) : 0;
                         const uint32_t s = wave_inclusive_sum32(d);
                         const uint64_t v = neg ? prev - s : prev + s;
-                        if (i < nd) out[n + 2 + i] = v;
+                        if (i < nd) out[n + 2 + i] = (T)v;
                         const uint32_t t = uni(readlane(s, kWave - 1));
                         prev = neg ? prev - t : prev + t;
                     }
@@ -593,7 +618,7 @@ __device__ __forceinline__ int decode_rle_v2_runs(InRing &in, uint32_t &pos, uin
                         uint64_t d = i < nd ? packed_value(in, p, i, w) : 0;
                         uint64_t s = wave_inclusive_sum(d);
                         uint64_t v = neg ? prev - s : prev + s;
-                        if (i < nd) out[n + 2 + i] = v;
+                        if (i < nd) out[n + 2 + i] = (T)v;
                         prev = uni64(readlane64(v, kWave - 1));
                     }
                 }
@@ -605,11 +630,52 @@ __device__ __forceinline__ int decode_rle_v2_runs(InRing &in, uint32_t &pos, uin
     return CODAG_OK;
 }
 
-__device__ __forceinline__ int decode_rle_v2(InRing &in, uint64_t *out, uint32_t cap) {
+template <class E = I64>
+__device__ __forceinline__ int decode_rle_v2(InRing &in, typename E::T *out, uint32_t cap) {
     uint32_t pos = in.skip, n = 0;
-    const int st = decode_rle_v2_runs(in, pos, in.gend, out, n, cap);
+    const int st = decode_rle_v2_runs<E>(in, pos, in.gend, out, n, cap);
     if (st) return st;
     return pos == in.gend ? CODAG_OK : CODAG_E_CORRUPT;
+}
+
+// ---- ORC byte RLE -------------------------------------------------------
+
+// Byte columns and PRESENT bitmaps: a header 0..127 is a run of header + 3
+// copies of the next byte, -1..-128 is followed by -header literal bytes.
+// Runs are written one byte per lane; literal bytes are copied from the
+// ring one per lane.  Checks in the order header, run byte, capacity, then
+// the literal bytes.
+template <class Ring>
+__device__ __forceinline__ int decode_byte_rle(Ring &in, uint8_t *out, uint32_t cap) {
+    uint32_t pos = in.skip, end = in.gend, n = 0;
+    const uint32_t l = lane();
+    while (n < cap) {
+        if (pos >= end) return CODAG_E_TRUNCATED;
+        in.ensure(pos + 136);
+        const uint64_t x = in.peek8(pos);
+        const uint32_t h = (uint32_t)(x & 0xff);
+        if (h < 128) {
+            const uint32_t len = h + 3;
+            if (pos + 2 > end) return CODAG_E_TRUNCATED;
+            if (n + len > cap) return CODAG_E_OVERFLOW;
+            const uint8_t b = (uint8_t)(x >> 8);
+            for (uint32_t i = l; i < len; i += kWave) out[n + i] = b;
+            pos += 2;
+            n += len;
+        } else {
+            const uint32_t len = 256 - h;
+            pos += 1;
+            if (n + len > cap) return CODAG_E_OVERFLOW;
+            if (pos + len > end) return CODAG_E_TRUNCATED;
+            for (uint32_t i = l; i < len; i += kWave) {
+                const uint32_t q = pos + i;
+                out[n + i] = (uint8_t)(in.word(q >> 2) >> (8 * (q & 3)));
+            }
+            pos += len;
+            n += len;
+        }
+    }
+    return pos == end ? CODAG_OK : CODAG_E_CORRUPT;
 }
 
 }  // namespace codag

@@ -68,8 +68,19 @@ def gpu_decode(codec, ch, dev, **kw):
 
 
 def _guard_status(codec):
-    st, _ = oracle.decode_chunk(int(codec), np.zeros(0, np.uint8), GUARD)
+    st, _ = oracle.decode_chunk(int(codec), np.zeros(0, np.uint8), GUARD) if codec != oracle.BYTE_RLE \
+        else (oracle.E_TRUNCATED, b"")
     return st
+
+
+def oracle_decode(codec, ch, threads=8, elem_bytes=0, unsigned_values=False):
+    """The oracle's decode of a chunk array, with the RLE element type."""
+    if codec == oracle.BYTE_RLE or elem_bytes not in (0, 8) or unsigned_values:
+        out, st, _ = oracle.decompress_ex(codec, ch.comp if ch.comp.size else np.zeros(16, np.uint8),
+                                          ch.chunk_offsets, ch.out_offsets,
+                                          elem_bytes=elem_bytes or 8, unsigned=bool(unsigned_values))
+        return out, st
+    return oracle.decompress(codec, ch.comp, ch.chunk_offsets, ch.out_offsets, threads=threads)
 
 
 def assert_parity(codec, ch, dev, threads=8, guards=True, **kw):
@@ -79,7 +90,7 @@ def assert_parity(codec, ch, dev, threads=8, guards=True, **kw):
     outside its range)."""
     import paper_2307_03760_amd as codag
     got, got_st = gpu_decode(codec, ch, dev, **kw)
-    ref, ref_st = oracle.decompress(codec, ch.comp, ch.chunk_offsets, ch.out_offsets, threads=threads)
+    ref, ref_st = oracle_decode(codec, ch, threads, kw.get("elem_bytes", 0), kw.get("unsigned_values", False))
     compare_chunks(got, got_st, ref, ref_st, ch.out_offsets)
     if guards:
         del got

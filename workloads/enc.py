@@ -74,3 +74,35 @@ def encode_rle_v2(values: np.ndarray, seg_len=None, seg_kind=None) -> bytes:
     n = lib.enc_rle_v2(v.ctypes.data, sl.ctypes.data if sl.size else 0,
                        sk.ctypes.data if sk.size else 0, sl.size, out.ctypes.data)
     return out[:n].tobytes()
+
+
+def encode_byte_rle(data: bytes) -> bytes:
+    """ORC byte RLE, greedy: a stretch of 3 or more equal bytes becomes runs
+    of up to 130 (header = length - 3, then the byte); everything else goes
+    out as literal lists of up to 128 bytes (header = -count)."""
+    b = bytes(data)
+    out = bytearray()
+    lit = bytearray()
+
+    def flush_lit():
+        while lit:
+            k = min(len(lit), 128)
+            out.append(256 - k)
+            out.extend(lit[:k])
+            del lit[:k]
+
+    i, n = 0, len(b)
+    while i < n:
+        j = i
+        while j < n and b[j] == b[i] and j - i < 130:
+            j += 1
+        if j - i >= 3:
+            flush_lit()
+            out.append(j - i - 3)
+            out.append(b[i])
+            i = j
+        else:
+            lit.append(b[i])
+            i += 1
+    flush_lit()
+    return bytes(out)
