@@ -25,7 +25,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-RLE_V1, RLE_V2, DEFLATE, BYTE_RLE = 1, 2, 3, 4
+RLE_V1, RLE_V2, DEFLATE, BYTE_RLE, LZ4 = 1, 2, 3, 4, 5
 OK, E_INVALID_ARGUMENT, E_CORRUPT, E_TRUNCATED, E_OVERFLOW, E_UNDERFLOW = 0, -1, -3, -4, -5, -6
 
 _lib = None
@@ -70,6 +70,10 @@ def _load():
             lib.oracle_orc_inflate_stream.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
                                                       ctypes.c_void_p, ctypes.c_uint64, u64p]
             lib.oracle_orc_inflate_stream.restype = ctypes.c_int
+            lib.oracle_orc_decompress_stream.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64,
+                                                         ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint64,
+                                                         u64p]
+            lib.oracle_orc_decompress_stream.restype = ctypes.c_int
             del u8p
             _lib = lib
     return _lib
@@ -160,13 +164,14 @@ def decompress_ex(codec: int, comp: np.ndarray, chunk_offsets: np.ndarray,
     return out, status, produced
 
 
-def orc_inflate_stream(framed: bytes | np.ndarray, block_size: int, out_cap: int):
-    """One compressed ORC stream (ZLIB codec): (status, decompressed bytes)."""
+def orc_inflate_stream(framed: bytes | np.ndarray, block_size: int, out_cap: int, codec: int = DEFLATE):
+    """One compressed ORC stream (ZLIB codec, or LZ4 with codec=LZ4):
+    (status, decompressed bytes)."""
     lib = _load()
     src = np.frombuffer(bytes(framed), dtype=np.uint8) if not isinstance(framed, np.ndarray) else framed
     src = np.ascontiguousarray(src, dtype=np.uint8)
     out = np.zeros(max(out_cap, 1), dtype=np.uint8)
     made = ctypes.c_uint64(0)
-    st = lib.oracle_orc_inflate_stream(_ptr(src), src.size, block_size, out.ctypes.data, out_cap,
-                                       ctypes.byref(made))
+    st = lib.oracle_orc_decompress_stream(codec, _ptr(src), src.size, block_size, out.ctypes.data,
+                                          out_cap, ctypes.byref(made))
     return st, bytes(out[: made.value])

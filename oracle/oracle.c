@@ -15,6 +15,8 @@
  *     DELTA sub-encodings.
  *   - Deflate (raw RFC 1951 stream per chunk): stored, fixed-Huffman and
  *     dynamic-Huffman blocks with LZ77 back-references.
+ *   - ORC byte RLE, and the LZ4 block format (a further LZ77 codec with
+ *     byte-aligned sequences and no entropy stage).
  *
  * Readings taken where the sources are silent (each is listed in the
  * design notes):
@@ -717,6 +719,74 @@ done:
 }
 
 /* ------------------------------------------------------------------ */
+/* LZ4 block format                                                      */
+/* ------------------------------------------------------------------ */
+/*
+ * A block is a sequence of sequences, each: a token byte (high nibble: the
+ * literal count, low nibble: the match length minus 4; a nibble of 15 is
+ * continued by bytes added to it until one below 255), the literals, then a
+ * 2-byte little-endian offset (1..65535, back from the current output end)
+ * and the match length's continuation bytes.  The block ends right after a
+ * sequence's literals.  Matches copy byte by byte, so one longer than its
+ * offset repeats the last `offset` bytes.  Checks in the order the fields
+ * are read: a field cut off by the end of input is TRUNCATED, offset 0 or
+ * an offset past the output produced so far is CORRUPT once the whole
+ * sequence header is read (there is no dictionary), output past the range
+ * is OVERFLOW (checked before the literals are read, as for a stored
+ * Deflate block), and the output must fill the range (UNDERFLOW otherwise)
+ * unless capacity_mode.
+ */
+static int lz4_length(byte_reader *r, uint64_t *len) {
+    uint8_t b;
+    do {
+        int st = br_byte(r, &b);
+        if (st) return st;
+        *len += b;
+    } while (b == 255);
+    return ORACLE_OK;
+}
+
+static int decode_lz4(const uint8_t *in, uint64_t in_len, uint8_t *out, uint64_t cap,
+                      uint64_t *n_out, int capacity_mode) {
+    byte_reader r = {in, in_len, 0};
+    uint64_t n = 0, k;
+    int st = ORACLE_OK;
+    for (;;) {
+        uint8_t tok, lo, hi;
+        uint64_t lit, mlen, off;
+        st = br_byte(&r, &tok);
+        if (st) goto done;
+        lit = tok >> 4;
+        if (lit == 15) {
+            st = lz4_length(&r, &lit);
+            if (st) goto done;
+        }
+        if (lit > cap - n) { st = ORACLE_E_OVERFLOW; goto done; }
+        if (r.len - r.pos < lit) { st = ORACLE_E_TRUNCATED; goto done; }
+        for (k = 0; k < lit; k++) out[n++] = r.buf[r.pos++];
+        if (r.pos == r.len) break; /* the last sequence has no match */
+        st = br_byte(&r, &lo);
+        if (st) goto done;
+        st = br_byte(&r, &hi);
+        if (st) goto done;
+        off = (uint64_t)lo | (uint64_t)hi << 8;
+        mlen = tok & 15;
+        if (mlen == 15) {
+            st = lz4_length(&r, &mlen);
+            if (st) goto done;
+        }
+        mlen += 4;
+        if (off == 0 || off > n) { st = ORACLE_E_CORRUPT; goto done; }
+        if (mlen > cap - n) { st = ORACLE_E_OVERFLOW; goto done; }
+        for (k = 0; k < mlen; k++, n++) out[n] = out[n - off];
+    }
+    if (n != cap && !capacity_mode) st = ORACLE_E_UNDERFLOW;
+done:
+    *n_out = n;
+    return st;
+}
+
+/* ------------------------------------------------------------------ */
 /* Entry points                                                         */
 /* ------------------------------------------------------------------ */
 
@@ -745,6 +815,11 @@ static int decode_one_chunk(int codec, const uint8_t *in, uint64_t in_len, uint8
     }
     if (codec == ORACLE_DEFLATE && c) {
         st = decode_deflate(in, in_len, out, out_cap, &n, c, capacity_mode);
+        *produced = n;
+        return st;
+    }
+    if (codec == ORACLE_LZ4) {
+        st = decode_lz4(in, in_len, out, out_cap, &n, capacity_mode);
         *produced = n;
         return st;
     }
@@ -789,7 +864,7 @@ int oracle_decompress_ex(int codec, int elem_bytes, int is_unsigned, int capacit
                          uint64_t *produced) {
     uint64_t i;
     code_set c;
-    if (codec < ORACLE_RLE_V1 || codec > ORACLE_BYTE_RLE || !valid_elem(elem_bytes)) return -1;
+    if (codec < ORACLE_RLE_V1 || codec > ORACLE_LZ4 || !valid_elem(elem_bytes)) return -1;
     if (n_chunks && (!comp || !chunk_offsets || !out || !out_offsets)) return -1;
     if (codec == ORACLE_DEFLATE && code_set_init(&c)) return -1;
     for (i = 0; i < n_chunks; i++) {
@@ -818,7 +893,8 @@ int oracle_decompress_ex(int codec, int elem_bytes, int is_unsigned, int capacit
  * A compressed ORC stream is a sequence of compression chunks, each a
  * 3-byte little-endian header (length << 1 | original) and `length` bytes:
  * the bytes themselves if `original` is set, else the chunk compressed on
- * its own -- for the ZLIB codec a raw Deflate stream.  Readings (the format
+ * its own -- for the ZLIB codec a raw Deflate stream, for the LZ4 codec an
+ * LZ4 block.  Readings (the format
  * leaves them open): every chunk but the last of a stream holds exactly
  * block_size uncompressed bytes, as Apache ORC's writers produce them (a
  * shorter one is UNDERFLOW, a longer one OVERFLOW); the last holds at most
@@ -828,11 +904,17 @@ int oracle_decompress_ex(int codec, int elem_bytes, int is_unsigned, int capacit
  */
 int oracle_orc_inflate_stream(const uint8_t *in, uint64_t in_len, uint64_t block_size,
                               uint8_t *out, uint64_t out_cap, uint64_t *out_len) {
+    return oracle_orc_decompress_stream(ORACLE_DEFLATE, in, in_len, block_size, out, out_cap, out_len);
+}
+
+int oracle_orc_decompress_stream(int codec, const uint8_t *in, uint64_t in_len, uint64_t block_size,
+                                 uint8_t *out, uint64_t out_cap, uint64_t *out_len) {
     uint64_t pos = 0, n = 0;
     code_set c;
     int st = ORACLE_OK;
     *out_len = 0;
     if (block_size == 0 || block_size >= (1u << 23)) return ORACLE_E_INVALID_ARGUMENT;
+    if (codec != ORACLE_DEFLATE && codec != ORACLE_LZ4) return ORACLE_E_INVALID_ARGUMENT;
     if (code_set_init(&c)) return ORACLE_E_INVALID_ARGUMENT;
     while (pos < in_len) {
         uint64_t h, len, room, made = 0;
@@ -850,7 +932,8 @@ int oracle_orc_inflate_stream(const uint8_t *in, uint64_t in_len, uint64_t block
             memcpy(out + n, in + pos, len);
             made = len;
         } else {
-            st = decode_deflate(in + pos, len, out + n, room, &made, &c, 1);
+            st = codec == ORACLE_DEFLATE ? decode_deflate(in + pos, len, out + n, room, &made, &c, 1)
+                                         : decode_lz4(in + pos, len, out + n, room, &made, 1);
             if (st) break;
         }
         if (!last && made != block_size) {

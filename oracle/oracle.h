@@ -28,6 +28,7 @@ extern "C" {
 #define ORACLE_RLE_V2 2
 #define ORACLE_DEFLATE 3
 #define ORACLE_BYTE_RLE 4
+#define ORACLE_LZ4 5
 
 /* Per-chunk status values (same numbering as the public library). */
 #define ORACLE_OK 0
@@ -63,8 +64,8 @@ int oracle_decompress(int codec, const uint8_t *comp,
  * delta base stays signed) -- and, with capacity_mode, Deflate output
  * ranges as upper bounds (status OK when the final block ends inside the
  * range).  produced[i] (may be NULL) receives chunk i's output bytes.
- * Codec ORACLE_BYTE_RLE decodes ORC byte RLE (elem_bytes and is_unsigned
- * ignored).
+ * Codec ORACLE_BYTE_RLE decodes ORC byte RLE and ORACLE_LZ4 the LZ4 block
+ * format (elem_bytes and is_unsigned ignored; LZ4 honours capacity_mode).
  */
 int oracle_decode_chunk_ex(int codec, int elem_bytes, int is_unsigned, int capacity_mode,
                            const uint8_t *in, uint64_t in_len, uint8_t *out, uint64_t out_cap,
@@ -82,6 +83,10 @@ int oracle_decompress_ex(int codec, int elem_bytes, int is_unsigned, int capacit
  */
 int oracle_orc_inflate_stream(const uint8_t *in, uint64_t in_len, uint64_t block_size,
                               uint8_t *out, uint64_t out_cap, uint64_t *out_len);
+/* The same for a stream whose compressed chunks are ORACLE_DEFLATE (ORC's
+ * ZLIB codec) or ORACLE_LZ4 (ORC's LZ4 codec: one LZ4 block per chunk). */
+int oracle_orc_decompress_stream(int codec, const uint8_t *in, uint64_t in_len, uint64_t block_size,
+                                 uint8_t *out, uint64_t out_cap, uint64_t *out_len);
 
 #ifdef __cplusplus
 }

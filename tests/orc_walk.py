@@ -137,11 +137,26 @@ def rle_v2_width_codes(stream: bytes):
     return codes
 
 
-def _unframe_meta(buf: bytes, compressed: bool) -> bytes:
-    """Metadata sections (footer, stripe footers) of a ZLIB-compressed file:
-    the compression chunks inflated with Python's zlib.  Test plumbing only
-    (the data streams go through the oracle and the GPU path)."""
-    if not compressed:
+def _lz4_block(chunk: bytes, cap: int) -> bytes:
+    """An LZ4 block through the oracle's decoder in capacity mode (its LZ4
+    decoder is pinned against pyarrow's on its own)."""
+    import numpy as np
+
+    import oracle
+    comp = np.frombuffer(bytes(chunk) + b"\0", dtype=np.uint8)
+    out, st, made = oracle.decompress_ex(oracle.LZ4, comp, np.array([0, len(chunk)], np.uint64),
+                                         np.array([0, cap], np.uint64), capacity=True)
+    if st[0] != oracle.OK:
+        raise ValueError("bad LZ4 metadata chunk")
+    return bytes(out[: int(made[0])])
+
+
+def _unframe_meta(buf: bytes, compression: int, block: int) -> bytes:
+    """Metadata sections (footer, stripe footers) of a compressed file: the
+    compression chunks inflated with Python's zlib (ZLIB) or expanded as LZ4
+    blocks (LZ4).  Test plumbing only (the data streams go through the
+    oracle and the GPU path)."""
+    if compression == 0:
         return buf
     import zlib
     out, pos = bytearray(), 0
@@ -151,8 +166,17 @@ def _unframe_meta(buf: bytes, compressed: bool) -> bytes:
         n = h >> 1
         chunk = buf[pos:pos + n]
         pos += n
-        out += chunk if h & 1 else zlib.decompress(chunk, -15)
+        if h & 1:
+            out += chunk
+        elif compression == ZLIB:
+            out += zlib.decompress(chunk, -15)
+        else:
+            out += _lz4_block(chunk, block)
     return bytes(out)
+
+
+# ORC compression kinds handled here (CompressionKind).
+NONE, ZLIB, LZ4 = 0, 1, 4
 
 
 # ORC stream kinds (Stream.Kind) and column encodings (ColumnEncoding.Kind).
@@ -162,15 +186,15 @@ DIRECT, DIRECT_V2 = 0, 2
 
 def file_streams(path: str):
     """The raw (still framed, if compressed) streams of every stripe:
-    {"compression": 0 none / 1 zlib, "block_size": int, "stripes": [
+    {"compression": 0 none / 1 zlib / 4 lz4, "block_size": int, "stripes": [
     {"rows": n, "streams": {(column, kind): bytes}, "encodings": [kind per column]}]}."""
     data = open(path, "rb").read()
     ps_len = data[-1]
     ps = dict((num, v) for num, _, v in _fields(data[-1 - ps_len:-1]))
     footer_len, compression, block = ps[1], ps.get(2, 0), ps.get(3, 256 * 1024)
-    if compression not in (0, 1):
-        raise ValueError("only uncompressed and ZLIB files")
-    footer = _unframe_meta(data[-1 - ps_len - footer_len:-1 - ps_len], compression == 1)
+    if compression not in (NONE, ZLIB, LZ4):
+        raise ValueError("only uncompressed, ZLIB and LZ4 files")
+    footer = _unframe_meta(data[-1 - ps_len - footer_len:-1 - ps_len], compression, block)
     stripes = []
     for num, _, v in _fields(footer):
         if num != 3:
@@ -178,7 +202,7 @@ def file_streams(path: str):
         info = {n: val for n, _, val in _fields(v)}
         offset, index_len, data_len, sf_len, rows = info[1], info.get(2, 0), info[3], info[4], info.get(5, 0)
         sf = _unframe_meta(data[offset + index_len + data_len:offset + index_len + data_len + sf_len],
-                           compression == 1)
+                           compression, block)
         streams, encodings, pos = {}, [], offset
         for n2, _, v2 in _fields(sf):
             if n2 == 1:
