@@ -6,7 +6,9 @@
  * is decoded by one decompression unit (here one 64-lane wavefront) whose
  * lanes all take part in decoding, reading and writing.  Codecs (Section
  * V-A): ORC integer RLE v1 and RLE v2 (signed int64 columns) and raw Deflate
- * (RFC 1951), one independent stream per chunk.
+ * (RFC 1951), one independent stream per chunk; beside them ORC byte RLE and
+ * LZ4 blocks, written against the same input and output primitives
+ * (Section III's extensibility: a codec is a device function over them).
  *
  * All entry points are plain C.  Buffers are caller-owned device memory;
  * the library never frees them and keeps no pointer to them once the
@@ -30,9 +32,13 @@ enum {
                            names another element type */
     CODAG_RLE_V2 = 2,   /* ORC integer RLE v2, likewise */
     CODAG_DEFLATE = 3,  /* raw RFC 1951 stream per chunk */
-    CODAG_BYTE_RLE = 4  /* ORC byte RLE (byte columns, PRESENT bitmaps): a header 0..127 is a
+    CODAG_BYTE_RLE = 4, /* ORC byte RLE (byte columns, PRESENT bitmaps): a header 0..127 is a
                            run of header + 3 copies of the next byte, -1..-128 is followed by
                            -header literal bytes; output is bytes */
+    CODAG_LZ4 = 5       /* one LZ4 block per chunk (the byte-aligned LZ77 codec ORC and Parquet
+                           call LZ4): sequences of a token byte, literals, a 2-byte offset of
+                           1..65535 and the match length; no dictionary, so an offset past the
+                           bytes already produced is CORRUPT; output is bytes */
 };
 
 /* Status codes: return values and per-chunk statuses. */
@@ -43,18 +49,18 @@ enum {
     CODAG_E_CORRUPT = -3,          /* the chunk's stream violates its format */
     CODAG_E_TRUNCATED = -4,        /* the chunk's stream ends before its output is complete */
     CODAG_E_OVERFLOW = -5,         /* the stream decodes to more bytes than the output range */
-    CODAG_E_UNDERFLOW = -6         /* Deflate: the final block ends before the output range is full */
+    CODAG_E_UNDERFLOW = -6         /* Deflate, LZ4: the stream ends before the output range is full */
 };
 
 /*
  * Tuning knobs; a zeroed struct (or NULL) selects the defaults.
  *   waves_per_block   wavefronts per workgroup: 1, 2 or 4 (default 1 for
- *                     Deflate, 4 for RLE); waves never synchronize with each
+ *                     Deflate and LZ4, 4 for RLE); waves never synchronize with each
  *                     other, so this only shapes occupancy and dispatch.
  *   lit_table_bits    Deflate literal/length lookup-table bits, 9 or 10
  *                     (default 9); longer codes take a slower path.
- *   history_kib       Deflate output window kept in LDS per wave: 2, 4, 8,
- *                     16 or 32 KiB (default 4).  Back-references reaching
+ *   history_kib       Deflate and LZ4 output window kept in LDS per wave: 2,
+ *                     4, 8, 16 or 32 KiB (default 4).  Back-references reaching
  *                     further read the already written output from HBM.
  *                     With 32 the workgroup holds one wave.
  *   chunk_ticks       optional device array (n_chunks uint64): receives each
@@ -71,7 +77,8 @@ enum {
  *                     v2 chunk -- then one wave per range decodes it.  The
  *                     path takes its workspace (272 bytes per RLE v1 chunk,
  *                     96 per RLE v2 chunk) from the stream-ordered allocator
- *                     (hipMallocAsync) on `stream`.  Ignored for Deflate.
+ *                     (hipMallocAsync) on `stream`.  Ignored for Deflate
+ *                     and LZ4.
  *   variant           0 = the decoders above.  The others are the decoding-
  *                     unit designs CODAG measures its own against, for
  *                     comparison on the same chunks (same output and
@@ -193,7 +200,7 @@ int codag_decompress_noalloc(int codec, const uint8_t *comp_buf, const uint64_t 
  * into out[0 .. out_cap) on the device.  The stream is a sequence of
  * compression chunks, each a 3-byte little-endian header (length << 1 |
  * original) and `length` bytes -- the bytes themselves if `original`, else
- * a raw Deflate stream.  Every chunk but the last holds exactly block_size
+ * a raw Deflate stream (codag_orc_decompress_stream: or an LZ4 block).  Every chunk but the last holds exactly block_size
  * uncompressed bytes (as Apache ORC's writers produce them; a shorter one
  * is CODAG_E_UNDERFLOW, a longer one CODAG_E_OVERFLOW), the last at most
  * block_size; a header or chunk cut off by the end of the stream is
@@ -214,6 +221,14 @@ int codag_decompress_noalloc(int codec, const uint8_t *comp_buf, const uint64_t 
 int codag_orc_inflate_stream(const uint8_t *framed, uint64_t framed_len, uint32_t block_size,
                              uint8_t *out, uint64_t out_cap, uint64_t *out_len, int32_t *status,
                              void *stream);
+
+/* As codag_orc_inflate_stream for a stream of either ORC codec the library
+ * decodes: codec CODAG_DEFLATE (ORC's ZLIB) or CODAG_LZ4 (ORC's LZ4, one
+ * LZ4 block per compression chunk); other codecs return
+ * CODAG_E_INVALID_ARGUMENT. */
+int codag_orc_decompress_stream(int codec, const uint8_t *framed, uint64_t framed_len,
+                                uint32_t block_size, uint8_t *out, uint64_t out_cap,
+                                uint64_t *out_len, int32_t *status, void *stream);
 
 /*
  * Return the status of the lowest-indexed chunk that failed in any call on
@@ -261,7 +276,8 @@ enum {
  *                     as many as the per-wave LDS allows, at most 16).
  *   waves_per_block   1, 2 or 4 (default 2).
  *   lit_table_bits    Deflate literal/length table bits; only 9 here.
- *   history_kib       Deflate LDS output window, 4, 8 or 16 KiB (default 4).
+ *   history_kib       Deflate and LZ4 LDS output window, 4, 8 or 16 KiB
+ *                     (default 4).
  *   order             CODAG_ORDER_* (default CODAG_ORDER_INDEX).
  *   use_graph         nonzero: capture the launch sequence (queue reset,
  *                     scheduling steps, decode) in a hipGraph once per set of
@@ -291,7 +307,7 @@ int codag_plan_set_opts(codag_plan *plan, const codag_batch_opts *opts);
 
 /*
  * Decompress n_chunks chunks whose codecs are codecs[i] (device, uint8,
- * CODAG_RLE_V1/V2/DEFLATE; anything else fails that chunk with
+ * CODAG_RLE_V1/V2/DEFLATE/LZ4; anything else fails that chunk with
  * CODAG_E_INVALID_ARGUMENT).  Buffers, offsets and output rules are those of
  * codag_decompress.
  *   chunk_status  device, n_chunks int32, may be NULL.

@@ -14,11 +14,10 @@ import threading
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcodag.so")
 
-RLE_V1, RLE_V2, DEFLATE = 1, 2, 3
 ORDER_INDEX, ORDER_GIVEN, ORDER_LEARNED = 0, 1, 2
 SCHED_FEATURES, SCHED_PARAMS, SCHED_NORM = 16, 5313, 34
 OK = 0
-RLE_V1, RLE_V2, DEFLATE, BYTE_RLE = 1, 2, 3, 4
+RLE_V1, RLE_V2, DEFLATE, BYTE_RLE, LZ4 = 1, 2, 3, 4, 5
 VARIANT_DEFAULT, VARIANT_LEADER_LANE, VARIANT_PREFETCH_WAVE, VARIANT_BLOCK_LEADER = 0, 1, 2, 3
 E_INVALID_ARGUMENT, E_HIP, E_CORRUPT, E_TRUNCATED, E_OVERFLOW, E_UNDERFLOW = -1, -2, -3, -4, -5, -6
 
@@ -64,6 +63,8 @@ def lib():
             L.codag_decompress_noalloc.restype = i32
             L.codag_orc_inflate_stream.argtypes = [vp, u64, ctypes.c_uint32, vp, u64, vp, vp, vp]
             L.codag_orc_inflate_stream.restype = i32
+            L.codag_orc_decompress_stream.argtypes = [i32, vp, u64, ctypes.c_uint32, vp, u64, vp, vp, vp]
+            L.codag_orc_decompress_stream.restype = i32
             L.codag_get_error.argtypes = [vp, ctypes.POINTER(u64)]
             L.codag_get_error.restype = i32
             L.codag_status_string.argtypes = [i32]
@@ -186,6 +187,21 @@ def orc_inflate_stream(framed, block_size: int, out, out_len, status, *, stream=
                                         _stream_handle(stream))
     if rc != OK:
         raise CodagError(rc, "codag_orc_inflate_stream")
+
+
+def orc_decompress_stream(codec: int, framed, block_size: int, out, out_len, status, *,
+                          stream=None) -> None:
+    """Enqueue codag_orc_decompress_stream: as orc_inflate_stream for a
+    stream of ORC's ZLIB (codec DEFLATE) or LZ4 (codec LZ4) codec."""
+    import torch
+    a = _check_dev(framed, "framed", (torch.uint8,))
+    b = _check_dev(out, "out", (torch.uint8,))
+    c = _check_dev(out_len, "out_len", (torch.int64,), 1)
+    d = _check_dev(status, "status", (torch.int32,), 1)
+    rc = lib().codag_orc_decompress_stream(int(codec), a, framed.numel(), int(block_size), b,
+                                           out.numel(), c, d, _stream_handle(stream))
+    if rc != OK:
+        raise CodagError(rc, "codag_orc_decompress_stream")
 
 
 def get_error(stream=None):

@@ -63,6 +63,10 @@ __global__ void __launch_bounds__(kWave * WPB)
         else if (codec == CODAG_DEFLATE)
             st = decode_one<CODAG_DEFLATE, TB, H>(comp, coff, out, ooff, c, s_ring[wave],
                                                   s_land[wave], &s_scratch[wave]);
+        else if (codec == CODAG_LZ4)
+            st = decode_one<CODAG_LZ4, TB, H>(
+                comp, coff, out, ooff, c, s_ring[wave], s_land[wave],
+                reinterpret_cast<WaveScratch<CODAG_LZ4, TB, H> *>(&s_scratch[wave]));
         else
             st = CODAG_E_INVALID_ARGUMENT;
         uint64_t t1 = __builtin_amdgcn_s_memtime();

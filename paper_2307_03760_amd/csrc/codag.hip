@@ -116,6 +116,20 @@ int launch_plain(const uint8_t *comp, const uint64_t *coff, uint8_t *out, const 
     }
 }
 
+// LZ4 keeps the Deflate window sizes (its offsets reach 64 KiB; farther
+// matches read the written output from HBM).
+int launch_lz4(const uint8_t *comp, const uint64_t *coff, uint8_t *out, const uint64_t *ooff,
+               uint64_t n, int wpb, int hist_kib, int32_t *status, unsigned long long *err,
+               uint64_t *ticks, hipStream_t stream) {
+    switch (hist_kib) {
+        case 2: return launch_plain<CODAG_LZ4, 9, 2048>(comp, coff, out, ooff, n, wpb, status, err, ticks, stream);
+        case 4: return launch_plain<CODAG_LZ4, 9, 4096>(comp, coff, out, ooff, n, wpb, status, err, ticks, stream);
+        case 8: return launch_plain<CODAG_LZ4, 9, 8192>(comp, coff, out, ooff, n, wpb, status, err, ticks, stream);
+        case 16: return launch_plain<CODAG_LZ4, 9, 16384>(comp, coff, out, ooff, n, wpb, status, err, ticks, stream);
+        default: return launch_wpb<CODAG_LZ4, 9, 32768, 1>(comp, coff, out, ooff, n, status, err, ticks, stream);
+    }
+}
+
 template <int TB>
 int launch_deflate(const uint8_t *comp, const uint64_t *coff, uint8_t *out, const uint64_t *ooff,
                    uint64_t n, int wpb, int hist_kib, int32_t *status, unsigned long long *err,
@@ -145,22 +159,22 @@ namespace {
 int decompress(int codec, const uint8_t *comp_buf, const uint64_t *chunk_offsets, uint8_t *out_buf,
                const uint64_t *out_offsets, uint64_t n_chunks, void *stream, int32_t *chunk_status,
                const codag_opts *opts, bool noalloc) {
-    if (codec != CODAG_RLE_V1 && codec != CODAG_RLE_V2 && codec != CODAG_DEFLATE &&
-        codec != CODAG_BYTE_RLE)
-        return CODAG_E_INVALID_ARGUMENT;
+    if (codec < CODAG_RLE_V1 || codec > CODAG_LZ4) return CODAG_E_INVALID_ARGUMENT;
+    const bool lz77 = codec == CODAG_DEFLATE || codec == CODAG_LZ4;
     const int eb = opts && opts->elem_bytes ? opts->elem_bytes : 8;
     const int uns = opts ? opts->unsigned_values : 0;
     if ((eb != 1 && eb != 2 && eb != 4 && eb != 8) || (uns != 0 && uns != 1)) return CODAG_E_INVALID_ARGUMENT;
     // Byte RLE, and RLE element types other than signed 8-byte values, take
     // the one-wave-per-chunk typed decoder.
-    const bool typed = codec == CODAG_BYTE_RLE || (codec != CODAG_DEFLATE && (eb != 8 || uns));
+    const bool typed = codec == CODAG_BYTE_RLE || (!lz77 && (eb != 8 || uns));
     if (typed && opts && (opts->variant || opts->group_parallel == 2)) return CODAG_E_INVALID_ARGUMENT;
     if (n_chunks == 0) return CODAG_OK;
     if (!comp_buf || !chunk_offsets || !out_buf || !out_offsets) return CODAG_E_INVALID_ARGUMENT;
     if (n_chunks >= (1ull << 32) - 64) return CODAG_E_INVALID_ARGUMENT;
-    // Defaults: RLE waves share a workgroup; Deflate waves go one per
-    // workgroup with a small window and table, for the most resident waves.
-    int wpb = opts && opts->waves_per_block ? opts->waves_per_block : codec == CODAG_DEFLATE ? 1 : 4;
+    // Defaults: RLE waves share a workgroup; Deflate and LZ4 waves go one
+    // per workgroup with a small window (and table), for the most resident
+    // waves.
+    int wpb = opts && opts->waves_per_block ? opts->waves_per_block : lz77 ? 1 : 4;
     int tb = opts && opts->lit_table_bits ? opts->lit_table_bits : 9;
     int hist = opts && opts->history_kib ? opts->history_kib : 4;
     if (opts && (opts->group_parallel < 0 || opts->group_parallel > 2)) return CODAG_E_INVALID_ARGUMENT;
@@ -207,6 +221,9 @@ int decompress(int codec, const uint8_t *comp_buf, const uint64_t *chunk_offsets
         }
             return launch_plain<CODAG_RLE_V2, 10, 0>(comp_buf, chunk_offsets, out_buf, out_offsets,
                                                      n_chunks, wpb, chunk_status, ds->err, ticks, s);
+        case CODAG_LZ4:
+            return launch_lz4(comp_buf, chunk_offsets, out_buf, out_offsets, n_chunks, wpb, hist,
+                              chunk_status, ds->err, ticks, s);
         default:
             if (tb == 9)
                 return launch_deflate<9>(comp_buf, chunk_offsets, out_buf, out_offsets, n_chunks,

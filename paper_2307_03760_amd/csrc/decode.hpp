@@ -3,6 +3,7 @@
 
 #include "../../include/codag.h"
 #include "deflate.hpp"
+#include "lz4.hpp"
 #include "rle.hpp"
 
 namespace codag {
@@ -17,6 +18,12 @@ struct WaveScratch {
 template <int TB, uint32_t H>
 struct WaveScratch<CODAG_DEFLATE, TB, H> {
     DeflateLds<TB, H> t;
+};
+// The LZ4 window is the first member of both, so a Deflate slice (as the
+// batched launch allocates) serves LZ4 too.
+template <int TB, uint32_t H>
+struct WaveScratch<CODAG_LZ4, TB, H> {
+    Lz4Lds<H> t;
 };
 
 __device__ __forceinline__ uint64_t error_key(uint64_t chunk, int st) {
@@ -41,6 +48,9 @@ __device__ __forceinline__ int decode_one(const uint8_t *comp, const uint64_t *c
         if (in_len >= (1u << 28)) return CODAG_E_INVALID_ARGUMENT;  // bit counts fit 31 bits
         in.init(comp + i0, in_len, ring, land);
         st = decode_deflate<TB, H>(in, dst, out_len, &scratch->t);
+    } else if constexpr (Codec == CODAG_LZ4) {
+        in.init(comp + i0, in_len, ring, land);
+        st = decode_lz4<H>(in, dst, out_len, &scratch->t);
     } else if constexpr (Codec == CODAG_BYTE_RLE) {
         in.init(comp + i0, in_len, ring, land);
         st = decode_byte_rle(in, dst, out_len);

@@ -114,13 +114,15 @@ __global__ void __launch_bounds__(kWave)
     }
 }
 
-// Chunk f (one wave per chunk, persistent grid) into out + f * block.
+// Chunk f (one wave per chunk, persistent grid) into out + f * block; a
+// compressed chunk is a raw Deflate stream (ZLIB) or an LZ4 block (LZ4).
+template <int Codec>
 __global__ void __launch_bounds__(kWave)
     orc_frame_decode(const uint8_t *framed, uint32_t block, uint8_t *out, uint64_t out_cap,
                      const OrcFrame *frames, OrcMeta *meta) {
     __shared__ __align__(16) uint32_t s_ring[kRingLdsWords];
     __shared__ __align__(16) uint32_t s_land[kLandWords];
-    __shared__ __align__(16) DeflateLds<9, 4096> s_lds;
+    __shared__ __align__(16) WaveScratch<Codec, 9, 4096> s_lds;
     const uint32_t count = uni(meta->count), complete = uni(meta->complete);
     for (uint32_t f = blockIdx.x; f < count; f += gridDim.x) {
         const uint64_t at = (uint64_t)f * block;
@@ -142,7 +144,10 @@ __global__ void __launch_bounds__(kWave)
         } else {
             InRing in;
             in.init(framed + src, len, s_ring, s_land);
-            st = decode_deflate<9, 4096>(in, out + at, room, &s_lds, &made);
+            if constexpr (Codec == CODAG_DEFLATE)
+                st = decode_deflate<9, 4096>(in, out + at, room, &s_lds.t, &made);
+            else
+                st = decode_lz4<4096>(in, out + at, room, &s_lds.t, &made);
             __builtin_amdgcn_s_waitcnt(0);
         }
         if (st == CODAG_OK && !last && made != block) st = made < block ? CODAG_E_UNDERFLOW : CODAG_E_OVERFLOW;
@@ -163,12 +168,12 @@ __global__ void orc_finish(uint32_t block, const OrcMeta *meta, uint64_t *out_le
 
 }  // namespace codag
 
-extern "C" int codag_orc_inflate_stream(const uint8_t *framed, uint64_t framed_len, uint32_t block_size,
-                                        uint8_t *out, uint64_t out_cap, uint64_t *out_len,
-                                        int32_t *status, void *stream) {
+extern "C" int codag_orc_decompress_stream(int codec, const uint8_t *framed, uint64_t framed_len,
+                                           uint32_t block_size, uint8_t *out, uint64_t out_cap,
+                                           uint64_t *out_len, int32_t *status, void *stream) {
     using namespace codag;
     if (!out_len || !status || (framed_len && (!framed || !out)) || block_size == 0 ||
-        block_size >= (1u << 23))
+        block_size >= (1u << 23) || (codec != CODAG_DEFLATE && codec != CODAG_LZ4))
         return CODAG_E_INVALID_ARGUMENT;
     const uint64_t max_frames64 = out_cap / block_size + 2;
     if (max_frames64 >= (1ull << 31)) return CODAG_E_INVALID_ARGUMENT;
@@ -181,10 +186,21 @@ extern "C" int codag_orc_inflate_stream(const uint8_t *framed, uint64_t framed_l
     OrcFrame *frames = reinterpret_cast<OrcFrame *>(static_cast<char *>(ws) + sizeof(OrcMeta));
     hipLaunchKernelGGL(orc_frames, dim3(1), dim3(kWave), 0, s, framed, framed_len, frames, max_frames, meta);
     const uint32_t grid = max_frames < 2048 ? max_frames : 2048;
-    hipLaunchKernelGGL(orc_frame_decode, dim3(grid), dim3(kWave), 0, s, framed, block_size, out, out_cap,
-                       frames, meta);
+    if (codec == CODAG_DEFLATE)
+        hipLaunchKernelGGL(orc_frame_decode<CODAG_DEFLATE>, dim3(grid), dim3(kWave), 0, s, framed,
+                           block_size, out, out_cap, frames, meta);
+    else
+        hipLaunchKernelGGL(orc_frame_decode<CODAG_LZ4>, dim3(grid), dim3(kWave), 0, s, framed,
+                           block_size, out, out_cap, frames, meta);
     hipLaunchKernelGGL(orc_finish, dim3(1), dim3(kWave), 0, s, block_size, meta, out_len, status);
     const hipError_t e = hipGetLastError();
     if (hipFreeAsync(ws, s) != hipSuccess) return CODAG_E_HIP;
     return e == hipSuccess ? CODAG_OK : CODAG_E_HIP;
+}
+
+extern "C" int codag_orc_inflate_stream(const uint8_t *framed, uint64_t framed_len, uint32_t block_size,
+                                        uint8_t *out, uint64_t out_cap, uint64_t *out_len,
+                                        int32_t *status, void *stream) {
+    return codag_orc_decompress_stream(CODAG_DEFLATE, framed, framed_len, block_size, out, out_cap,
+                                       out_len, status, stream);
 }

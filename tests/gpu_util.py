@@ -36,7 +36,7 @@ def guarded(ch):
     oo[1::2] = src + GUARD * (k + 1)
     # Guards take their neighbour's codec when it is a valid one.
     own = np.asarray(ch.codecs, dtype=np.uint8)
-    gc = np.where((own >= 1) & (own <= 3), own, 1).astype(np.uint8)
+    gc = np.where((own >= 1) & (own <= 5), own, 1).astype(np.uint8)
     codecs = np.ones(2 * n + 1, dtype=np.uint8)
     codecs[1::2] = own
     codecs[0:2 * n:2] = gc
@@ -68,8 +68,7 @@ def gpu_decode(codec, ch, dev, **kw):
 
 
 def _guard_status(codec):
-    st, _ = oracle.decode_chunk(int(codec), np.zeros(0, np.uint8), GUARD) if codec != oracle.BYTE_RLE \
-        else (oracle.E_TRUNCATED, b"")
+    st, _ = oracle.decode_chunk(int(codec), np.zeros(0, np.uint8), GUARD)
     return st
 
 
@@ -130,7 +129,7 @@ def oracle_mixed(codecs, comp, chunk_offsets, out_offsets, threads=8):
         while b < n and codecs[b] == codecs[a]:
             b += 1
         c = int(codecs[a])
-        if c in (oracle.RLE_V1, oracle.RLE_V2, oracle.DEFLATE):
+        if c in (oracle.RLE_V1, oracle.RLE_V2, oracle.DEFLATE, oracle.LZ4):
             o, s = oracle.decompress(c, comp, chunk_offsets[a:b + 1], out_offsets[a:b + 1],
                                      threads=threads)
             lo, hi = int(out_offsets[a]), int(out_offsets[b])

@@ -3,8 +3,9 @@
 Pinned three ways, none of which reuses the oracle's own code:
   - blocks written by pyarrow's LZ4 (the reference LZ4 library's block
     compressor) over the workload's data classes must decode to the data;
-  - blocks written by a small greedy encoder here (long matches, offsets up
-    to 65535, overlapping copies, literal runs past 15 and 270) must decode
+  - blocks written by a small greedy encoder (workloads/lz4enc.py: long
+    matches, offsets up to 65535, overlapping copies, literal runs past 15
+    and 270) must decode
     through pyarrow's LZ4 to the data, and through the oracle to the same;
   - hand-worked blocks (tests/golden/lz4_hand_streams.json), including the
     error statuses, worked out from the block format by hand.
@@ -19,6 +20,7 @@ import pytest
 
 import oracle
 from orc_walk import DATA, DIRECT_V2, LENGTH, file_streams
+from workloads.lz4enc import lz4_greedy
 
 pa = pytest.importorskip("pyarrow")
 po = pytest.importorskip("pyarrow.orc")
@@ -57,49 +59,6 @@ def _data(kind, n, rng):
     return bytes(n)
 
 
-def _greedy_encode(data: bytes, max_off: int = 65535, min_tail: int = 5) -> bytes:
-    """A small LZ4 block encoder: hash of 4 bytes -> last position, greedy
-    matches extended forward.  Keeps the format's end rules (the last 5
-    bytes are literals, no match starts in the last 12) so that the
-    reference decoder accepts its output."""
-    n, out, table = len(data), bytearray(), {}
-    anchor = i = 0
-    limit = n - 12
-
-    def length_bytes(v):
-        while v >= 255:
-            out.append(255)
-            v -= 255
-        out.append(v)
-
-    while i < limit:
-        key = data[i:i + 4]
-        j = table.get(key)
-        table[key] = i
-        if j is None or i - j > max_off:
-            i += 1
-            continue
-        m = 4
-        while i + m < n - min_tail and data[j + m] == data[i + m]:
-            m += 1
-        lit = i - anchor
-        out.append((min(lit, 15) << 4) | min(m - 4, 15))
-        if lit >= 15:
-            length_bytes(lit - 15)
-        out += data[anchor:i]
-        out += (i - j).to_bytes(2, "little")
-        if m - 4 >= 15:
-            length_bytes(m - 4 - 15)
-        i += m
-        anchor = i
-    lit = n - anchor
-    out.append(min(lit, 15) << 4)
-    if lit >= 15:
-        length_bytes(lit - 15)
-    out += data[anchor:]
-    return bytes(out)
-
-
 @pytest.mark.parametrize("kind", ["zipf", "int32", "random", "runs", "text", "zeros"])
 @pytest.mark.parametrize("n", [0, 1, 13, 4096, 65536, 300_001])
 def test_pyarrow_blocks_decode(kind, n):
@@ -126,7 +85,7 @@ def _greedy_cases():
 @pytest.mark.parametrize("name", sorted(_greedy_cases()))
 def test_greedy_blocks_both_decoders(name):
     data = _greedy_cases()[name]
-    block = _greedy_encode(data)
+    block = lz4_greedy(data)
     ref = pa.Codec("lz4_raw").decompress(block, decompressed_size=len(data), asbytes=True)
     assert ref == data  # the encoder here writes valid blocks
     st, out = _one(block, len(data))
@@ -173,7 +132,7 @@ def test_capacity_mode_and_chunk_ranges():
 
 def test_every_truncation_is_an_error():
     data = b"abcabcabcabcXYZXYZXYZ" * 30 + b"0123456789"
-    block = _greedy_encode(data)
+    block = lz4_greedy(data)
     for cut in range(len(block)):
         st, out = _one(block[:cut], len(data))
         assert st in (oracle.E_TRUNCATED, oracle.E_UNDERFLOW), cut

@@ -18,6 +18,8 @@ of the stated shapes:
   random lowercase vocabulary, 30% little-endian int32 columns of 64 distinct
   values, 20% uniform random bytes; zlib level 9 raw deflate (window 32 KiB),
   a seeded third of the compressible chunks with fixed Huffman codes only.
+* ``lz4`` -- the ``deflate`` workload's chunks (same classes, same bytes)
+  as LZ4 blocks from the reference LZ4 compressor (through pyarrow).
 * ``batched`` -- mixed codecs (40/30/30) with log-normal chunk sizes
   (median 64 KiB, clipped to 4 KiB..1 MiB).
 * ``learned`` -- Deflate chunks with skewed ratios: random, Zipf text and
@@ -37,7 +39,7 @@ import numpy as np
 from . import enc
 from .enc import AUTO, DELTA, DIRECT, PATCHED_BASE, SHORT_REPEAT  # noqa: F401
 
-RLE_V1, RLE_V2, DEFLATE = 1, 2, 3
+RLE_V1, RLE_V2, DEFLATE, LZ4 = 1, 2, 3, 5
 WL_RLE_V1, WL_RLE_V2, WL_DEFLATE, WL_BATCHED, WL_LEARNED = 1, 2, 3, 4, 5
 
 
@@ -298,8 +300,13 @@ def deflate_raw(data: bytes, level: int = 9, fixed: bool = False) -> bytes:
 ZIPF, INT32, RANDOM, INT32_RUNS = 0, 1, 2, 3
 
 
-def _deflate_chunk(args):
-    seed, wl, j, size, klass, fixed_share = args
+def lz4_block(data: bytes) -> bytes:
+    """One LZ4 block (the reference LZ4 library's compressor, via pyarrow)."""
+    import pyarrow as pa
+    return pa.Codec("lz4_raw").compress(data, asbytes=True)
+
+
+def _class_data(seed, wl, j, size, klass):
     rng = np.random.default_rng([seed, wl, j])
     if klass == ZIPF:
         data = zipf_text(size, rng, _vocab(seed))
@@ -309,8 +316,19 @@ def _deflate_chunk(args):
         data = int32_column(size, rng, run_heavy=True)
     else:
         data = random_bytes(size, rng)
+    return data, rng
+
+
+def _deflate_chunk(args):
+    seed, wl, j, size, klass, fixed_share = args
+    data, rng = _class_data(seed, wl, j, size, klass)
     fixed = klass != RANDOM and rng.random() < fixed_share
     return deflate_raw(data, 9, fixed), fixed
+
+
+def _lz4_chunk(args):
+    seed, wl, j, size, klass = args
+    return lz4_block(_class_data(seed, wl, j, size, klass)[0])
 
 
 def _map(fn, items, nproc=None):
@@ -363,6 +381,20 @@ def deflate_workload(seed: int = 0, total_bytes: int = 1 << 30, chunk_bytes: int
     ch.info.update(workload="deflate", total_bytes=n * chunk_bytes, chunk_bytes=chunk_bytes,
                    seed=seed, classes=classes.astype(np.uint8),
                    fixed_chunks=int(sum(r[1] for r in res)))
+    return ch
+
+
+def lz4_workload(seed: int = 0, total_bytes: int = 1 << 30, chunk_bytes: int = 65536) -> Chunked:
+    """The Deflate workload's chunks (same content classes, same bytes) as
+    LZ4 blocks."""
+    n = total_bytes // chunk_bytes
+    crng = np.random.default_rng([seed, WL_DEFLATE])
+    classes = crng.choice(3, size=n, p=[0.5, 0.3, 0.2])
+    items = [(seed, WL_DEFLATE, j, chunk_bytes, int(classes[j])) for j in range(n)]
+    blobs = _map(_lz4_chunk, items)
+    ch = _pack([LZ4] * n, blobs, [chunk_bytes] * n)
+    ch.info.update(workload="lz4", total_bytes=n * chunk_bytes, chunk_bytes=chunk_bytes, seed=seed,
+                   classes=classes.astype(np.uint8))
     return ch
 
 
