@@ -37,6 +37,8 @@ WORKLOADS = {
     "deflate": ("Deflate, 1 GiB in 64 KiB chunks (16384): 50% Zipf text, 30% int32 columns, "
                 "20% random bytes; zlib level 9, a third of compressible chunks fixed-Huffman, "
                 "seed 0", "u8"),
+    "lz4": ("LZ4 blocks: the Deflate workload's 16384 chunks of 64 KiB (same content), each "
+            "compressed by the reference LZ4 block compressor (pyarrow), seed 0", "u8"),
     "batched": ("Batched mixed launch: 20,000 chunks, 40% RLE v1 / 30% RLE v2 / 30% Deflate, "
                 "output sizes log-normal (median 64 KiB, 4 KiB-1 MiB), seed 0; one persistent "
                 "graph-captured autotuned launch vs one plain launch per codec", "mixed"),
@@ -46,20 +48,22 @@ WORKLOADS = {
 }
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "decode_plain_rle_v2_hbm_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "rle_v2_group_parallel_hbm_traffic.md")
+# The sources the headline's kernels (rle_v2_index, rle_v2_ranges,
+# split_finish) are built from.
+HEADLINE_SOURCES = ("split.hip", "rle.hpp", "stream.hpp", "wave.hpp", "internal.hpp")
 
 
-def sources_digest() -> str:
-    """SHA-256 over the HIP sources, so counter readings taken on other
+def sources_digest(files=HEADLINE_SOURCES) -> str:
+    """SHA-256 over the named HIP sources, so counter readings taken on other
     sources are not reported."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2307_03760_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(f.encode())
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+    for f in sorted(files):
+        h.update(f.encode())
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
@@ -88,6 +92,8 @@ def make_workload(name: str):
         return workloads.rle_v2_workload(seed=0, n_values=1 << 28)
     if name == "deflate":
         return workloads.deflate_workload(seed=0)
+    if name == "lz4":
+        return workloads.lz4_workload(seed=0)
     if name == "batched":
         return workloads.batched_workload(seed=0)
     if name == "learned":
@@ -298,7 +304,8 @@ def time_workload(name, ch, steps, warmup, dev, flush_buf=None):
     alg_bytes = ch.comp_bytes + out_bytes + 16 * ch.n_chunks
     res = {
         "workload": WORKLOADS[name][0],
-        "codec": {1: "rle_v1", 2: "rle_v2", 3: "deflate"}[codec],
+        "codec": {1: "rle_v1", 2: "rle_v2", 3: "deflate", 5: "lz4"}[codec],
+        "launch": launch_description(codec, ch.n_chunks),
         "n_chunks": ch.n_chunks,
         "out_bytes": out_bytes,
         "comp_bytes": ch.comp_bytes,
@@ -313,6 +320,22 @@ def time_workload(name, ch, steps, warmup, dev, flush_buf=None):
         res["cold_ms_per_launch"] = cold_ms
         res["cold_gbps"] = out_bytes / (cold_ms * 1e-3) / 1e9
     return res, out
+
+
+def launch_description(codec: int, n_chunks: int) -> str:
+    """What codag_decompress enqueues for this codec and chunk count with
+    default options."""
+    if codec == 2 and n_chunks <= 2048:
+        return ("group-parallel: rle_v2_index (one wave per chunk parses run headers and cuts the "
+                "chunk into 8 ranges) + rle_v2_ranges (one wave per range) + split_finish")
+    if codec == 1 and n_chunks <= 256:
+        return ("group-parallel: rle_v1_index (a 16-wave workgroup per chunk finds group starts "
+                "and cuts 16 ranges) + rle_v1_groups (one wave per range) + split_finish")
+    if codec == 3:
+        return "decode_plain<DEFLATE>: one wave64 per chunk, 1 wave per workgroup, 4 KiB LDS window"
+    if codec == 5:
+        return "decode_plain<LZ4>: one wave64 per chunk, 1 wave per workgroup, 2 KiB LDS window"
+    return "decode_plain: one wave64 per chunk, 4 waves per workgroup"
 
 
 ABLATIONS = {  # codag_opts.variant per decoding-unit design (the paper's Sections V-E, V-F, II-C)
@@ -422,7 +445,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rle_v2", choices=sorted(WORKLOADS))
-    ap.add_argument("--extras", default="rle_v1,rle_v1_scaled,rle_v2_scaled,deflate,batched,learned",
+    ap.add_argument("--extras", default="rle_v1,rle_v1_scaled,rle_v2_scaled,deflate,lz4,batched,learned",
                     help="comma-separated workloads also timed (empty for none)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="oracle time for the headline baseline (the per-codec oracle timings "
@@ -484,7 +507,7 @@ def main():
             r, o = time_workload(name, c2, args.steps, args.warmup, dev, flush)
             if name in ("rle_v1", "rle_v1_scaled", "deflate") and not args.no_ablations:
                 r["ablations"] = time_ablations(c2, dev)
-            if not args.no_cpu_baseline and name in ("rle_v1", "deflate"):
+            if not args.no_cpu_baseline and name in ("rle_v1", "deflate", "lz4"):
                 o_np = o.cpu().numpy()
                 r["cpu_oracle"] = {
                     "threads_1": cpu_baseline(name, c2, o_np, args.cpu_seconds / 4, threads=1),
@@ -510,8 +533,10 @@ def main():
         "data": "synthetic (seeded generators standing in for the paper's datasets)",
         "config": {"workload": head["workload"], "chunks": head["n_chunks"],
                    "out_bytes": head["out_bytes"], "comp_bytes": head["comp_bytes"],
-                   "launch": "plain, one wave64 per chunk, 4 waves per workgroup"},
+                   "launch": head["launch"]},
         "roofline": {
+            "kernel": "the whole codag_decompress call (" + head["launch"] + "): achieved uses "
+                      "the call's event time, so it understates the dominant kernel's rate",
             "bound": "hbm",
             "achieved": head["hbm_gbps"],
             "peak": HBM_PEAK_GBPS,
@@ -521,6 +546,7 @@ def main():
         },
         "per_workload": per,
         "paper_context": {"a100_gbps": {"rle_v1": 38.07, "rle_v2": 26.87, "deflate": 51.96},
+                          "note": "LZ4 is not among the paper's codecs",
                           "speedup_over_rapids_a100": {"rle_v1": 13.46, "rle_v2": 5.69,
                                                        "deflate": 1.18}},
         "generation_s": gen_s,

@@ -60,7 +60,8 @@ enum {
  *   lit_table_bits    Deflate literal/length lookup-table bits, 9 or 10
  *                     (default 9); longer codes take a slower path.
  *   history_kib       Deflate and LZ4 output window kept in LDS per wave: 2,
- *                     4, 8, 16 or 32 KiB (default 4).  Back-references reaching
+ *                     4, 8, 16 or 32 KiB (default 4 for Deflate, 2 for
+ *                     LZ4).  Back-references reaching
  *                     further read the already written output from HBM.
  *                     With 32 the workgroup holds one wave.
  *   chunk_ticks       optional device array (n_chunks uint64): receives each

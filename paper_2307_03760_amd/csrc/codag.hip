@@ -176,7 +176,9 @@ int decompress(int codec, const uint8_t *comp_buf, const uint64_t *chunk_offsets
     // waves.
     int wpb = opts && opts->waves_per_block ? opts->waves_per_block : lz77 ? 1 : 4;
     int tb = opts && opts->lit_table_bits ? opts->lit_table_bits : 9;
-    int hist = opts && opts->history_kib ? opts->history_kib : 4;
+    // LZ4 batches fit a 2 KiB window, and the smaller window keeps more
+    // waves resident; Deflate's token batches want 4 KiB.
+    int hist = opts && opts->history_kib ? opts->history_kib : codec == CODAG_LZ4 ? 2 : 4;
     if (opts && (opts->group_parallel < 0 || opts->group_parallel > 2)) return CODAG_E_INVALID_ARGUMENT;
     if (opts && opts->group_parallel == 2 && opts->chunk_ticks) return CODAG_E_INVALID_ARGUMENT;
     if ((wpb != 1 && wpb != 2 && wpb != 4) || (tb != 9 && tb != 10) ||

@@ -137,18 +137,35 @@ __device__ __forceinline__ int lz4_sequence(Ring &in, WindowOut<H> &o, uint32_t 
     return kLz4More;
 }
 
+// Value of v in lane `from` (0..63), for every lane at once.  A permute
+// reads 0 from a lane that is switched off, so every call is made with all
+// lanes on and the caller selects afterwards.
+__device__ __forceinline__ uint32_t lz4_pull(uint32_t v, uint32_t from) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)((from & 63) << 2), (int)v);
+}
+// Where the link `at` leads on in table v (64 stays 64).
+__device__ __forceinline__ uint32_t lz4_follow(uint32_t v, uint32_t at) {
+    const uint32_t r = lz4_pull(v, at);
+    return at < 64 ? r : 64u;
+}
+__device__ __forceinline__ uint64_t lz4_bit(uint32_t x) { return x < 64 ? 1ull << x : 0ull; }
+
 // Batches of short sequences.  Every lane parses the sequence that would
 // start at its own byte of a 64-byte input window (only short fields: at
-// most 14 literals, a match of at most 18 bytes) and packs its input length,
-// output length, literal count and offset into one word.  A wave-uniform
-// walk then follows the real sequence starts with one lane read each and
-// stops before anything the general step must judge: a long field, the
-// block's last sequence, a cut-off stream, output past the range, an offset
-// past the bytes produced.  The batch (at most 21 sequences, 672 output
-// bytes) is then written with the lanes of its sequences: all literals
-// first, then every match whose source lies before the batch (from the LDS
-// window, or from output already flushed to HBM), then, in order, the
-// matches that read the batch's own output.
+// most 14 literals, a match of at most 18 bytes).  The real sequence starts
+// are the chain of next-start links from the window's first byte; each lane
+// gathers, by lane permutes, where its links lead over eight steps and which
+// lanes they pass, so a wave-uniform walk covers eight sequences with two
+// lane reads.  The batch is the chain's prefix up to anything the general
+// step must judge: a long field, the block's last sequence, a cut-off
+// stream, output past the range, an offset reaching before the chunk's
+// output (the last two found with a prefix sum over the chain).  It holds at
+// most 21 sequences and 672 output bytes and is written with the lanes of
+// its sequences: all literals first, then every match whose source lies
+// before the batch (from the LDS window, or from output already flushed to
+// HBM), then the matches that read the batch's own output, in rounds: each
+// round copies every pending match whose source ends before the lowest
+// pending match's output, the bytes before that being final.
 template <uint32_t H, class Ring>
 __device__ __forceinline__ int decode_lz4(Ring &in, uint8_t *out, uint32_t cap, Lz4Lds<H> *lds,
                                           uint32_t *made = nullptr) {
@@ -174,42 +191,50 @@ __device__ __forceinline__ int decode_lz4(Ring &in, uint8_t *out, uint32_t cap, 
         const uint32_t lo = k < 4 ? g0 : k < 8 ? g1 : k < 12 ? g2 : g3;
         const uint32_t hi = k < 3 ? g0 : k < 7 ? g1 : k < 11 ? g2 : k < 15 ? g3 : g4;
         const uint32_t off = ((lo >> (8 * (k & 3))) & 255) | (((hi >> (8 * ((k + 1) & 3))) & 255) << 8);
-        const uint32_t outl = lit + ml + 4;
+        const uint32_t inl = 3 + lit, outl = lit + ml + 4, mlen = ml + 4;
         // What a sequence needs on its own: short fields, a nonzero offset,
         // its bytes inside the chunk and followed by more (the last sequence
-        // has no offset); and, packed for the walk, its input and output
-        // lengths and how many bytes must precede it for the offset to stay
-        // inside the chunk's output.
-        const bool ok = lit < 15 && ml < 15 && off != 0 && x + 3 + lit <= end;
-        const uint32_t need = off > lit ? off - lit : 0u;
-        const uint32_t packed = ok ? (3 + lit) | outl << 5 | need << 11 : 0u;
-
-        // The walk.
-        uint32_t s = 0, orel = 0;
+        // has no offset).
+        const bool ok = lit < 15 && ml < 15 && off != 0 && x + inl <= end;
+        // Links: the next start (64 = none in this window, or stop here).
+        const uint32_t n1 = ok ? min(l + inl, 64u) : 64u;
+        const uint32_t n2 = lz4_follow(n1, n1);
+        const uint32_t n3 = lz4_follow(n1, n2);
+        const uint32_t n4 = lz4_follow(n1, n3);
+        const uint64_t m4 = lz4_bit(l) | lz4_bit(n1) | lz4_bit(n2) | lz4_bit(n3);
+        const uint32_t n8 = lz4_follow(n4, n4);
+        const uint32_t m8h = lz4_pull((uint32_t)(m4 >> 32), n4), m8l = lz4_pull((uint32_t)m4, n4);
+        const uint64_t m8 = m4 | (n4 < 64 ? (uint64_t)m8h << 32 | m8l : 0ull);
+        // Links only lead forward, so eight steps of eight cover the window;
+        // the bound is a second guard.
         uint64_t chain = 0;
-        const uint32_t room_cap = cap - o.pos, pos0 = o.pos;
-        while (s < (uint32_t)kWave) {
-            const uint32_t v = readlane(packed, s);
-            const uint32_t inl = v & 31, nr = orel + ((v >> 5) & 63);
-            if (inl == 0 || nr > room_cap || (v >> 11) > pos0 + orel) break;
-            chain |= 1ull << s;
-            orel = nr;
-            s += inl;
+        for (uint32_t t = 0, step = 0; t < 64 && step < 8; step++) {
+            chain |= readlane64(m8, t);
+            t = readlane(n8, t);
         }
-        if (!chain) {
+        // The chain runs through sequences that are fine on their own and
+        // ends at (and includes) the first that is not, if any.
+        uint64_t exe = chain & ballot(ok);
+        const bool on = (exe >> l) & 1;
+        const uint32_t my_out = on ? outl : 0u;
+        const uint32_t incl = wave_inclusive_sum32(my_out), before = incl - my_out;
+        const uint64_t fm = ballot(on && (incl > cap - o.pos || (off > lit && off - lit > o.pos + before)));
+        if (fm) exe &= (fm & (0 - fm)) - 1;
+        if (!exe) {
             st = lz4_sequence(in, o, p, end, cap);
             if (st != kLz4More) break;
             st = CODAG_OK;
             continue;
         }
+        const uint32_t last = 63 - (uint32_t)__builtin_clzll(exe);
+        const uint32_t orel = readlane(incl, last);
+        const uint32_t s_end = last + 3 + (readlane(tok, last) >> 4);
 
-        const bool mine = (chain >> l) & 1;
-        const uint32_t my_out = mine ? outl : 0u;
-        const uint32_t excl = wave_inclusive_sum32(my_out) - my_out;
+        const bool mine = (exe >> l) & 1;
         o.make_room(orel);
         const uint32_t bo = o.o0 + o.pos;  // the batch's first output byte
-        const uint32_t dl = bo + excl;     // this sequence's literals
-        const uint32_t mlen = ml + 4, dm = dl + lit, src = dm - off;
+        const uint32_t dl = bo + before;   // this sequence's literals
+        const uint32_t dm = dl + lit, src = dm - off;
         // Literals (byte 1 + i of the candidate is literal i).
         for (uint32_t i = 0; i < 14; i++) {
             if (!ballot(mine && i < lit)) break;
@@ -240,24 +265,41 @@ __device__ __forceinline__ int decode_lz4(Ring &in, uint8_t *out, uint32_t cap, 
             for (uint32_t t = 0; t < 6; t++)
                 if (indep && i + t < mlen) o.win[o.slot(dm + i + t)] = v[t];
         }
-        // Matches that read the batch, in sequence order; a match longer than
-        // its offset repeats its first `off` bytes, one period at a time.
-        uint64_t dep = ballot(mine && !indep);
-        while (dep) {
-            const uint32_t t = (uint32_t)__builtin_ctzll(dep);
-            dep &= dep - 1;
-            const uint32_t md = readlane(dm, t), ms = readlane(src, t), mn = readlane(mlen, t),
-                           mo = readlane(off, t);
-            for (uint32_t i = 0; i < mn; i += mo) {
-                const uint32_t n = min(mo, mn - i);
-                uint8_t v = 0;
-                if (l < n) v = o.win[o.slot(ms + i + l)];
-                if (l < n) o.win[o.slot(md + i + l)] = v;
+        // Matches that read the batch (their sources are all in the window).
+        uint64_t pend = ballot(mine && !indep);
+        while (pend) {
+            const uint32_t t = (uint32_t)__builtin_ctzll(pend);
+            const uint32_t front = readlane(dm, t);
+            const bool ready = ((pend >> l) & 1) && src + mlen <= front;
+            const uint64_t rm = ballot(ready);
+            if (!rm) {
+                // The lowest pending match overlaps its own output: it
+                // repeats its first `off` bytes, one period at a time.
+                const uint32_t mo = readlane(off, t), mn = readlane(mlen, t), ms = front - mo;
+                for (uint32_t i = 0; i < mn; i += mo) {
+                    const uint32_t n = min(mo, mn - i);
+                    uint8_t v = 0;
+                    if (l < n) v = o.win[o.slot(ms + i + l)];
+                    if (l < n) o.win[o.slot(front + i + l)] = v;
+                }
+                pend &= pend - 1;
+                continue;
             }
+            for (uint32_t i = 0; i < 18; i += 6) {
+                if (!ballot(ready && i < mlen)) break;
+                uint8_t v[6];
+#pragma unroll
+                for (uint32_t t2 = 0; t2 < 6; t2++)
+                    v[t2] = ready && i + t2 < mlen ? o.win[o.slot(src + i + t2)] : 0;
+#pragma unroll
+                for (uint32_t t2 = 0; t2 < 6; t2++)
+                    if (ready && i + t2 < mlen) o.win[o.slot(dm + i + t2)] = v[t2];
+            }
+            pend &= ~rm;
         }
         o.pos += orel;
         o.room -= orel;
-        p += s;
+        p += s_end;
     }
     o.finish();
     if (st) return st;
