@@ -137,17 +137,6 @@ __device__ __forceinline__ int lz4_sequence(Ring &in, WindowOut<H> &o, uint32_t 
     return kLz4More;
 }
 
-// Value of v in lane `from` (0..63), for every lane at once.  A permute
-// reads 0 from a lane that is switched off, so every call is made with all
-// lanes on and the caller selects afterwards.
-__device__ __forceinline__ uint32_t lz4_pull(uint32_t v, uint32_t from) {
-    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)((from & 63) << 2), (int)v);
-}
-// Where the link `at` leads on in table v (64 stays 64).
-__device__ __forceinline__ uint32_t lz4_follow(uint32_t v, uint32_t at) {
-    const uint32_t r = lz4_pull(v, at);
-    return at < 64 ? r : 64u;
-}
 __device__ __forceinline__ uint64_t lz4_bit(uint32_t x) { return x < 64 ? 1ull << x : 0ull; }
 
 // Batches of short sequences.  Every lane parses the sequence that would
@@ -198,12 +187,12 @@ __device__ __forceinline__ int decode_lz4(Ring &in, uint8_t *out, uint32_t cap, 
         const bool ok = lit < 15 && ml < 15 && off != 0 && x + inl <= end;
         // Links: the next start (64 = none in this window, or stop here).
         const uint32_t n1 = ok ? min(l + inl, 64u) : 64u;
-        const uint32_t n2 = lz4_follow(n1, n1);
-        const uint32_t n3 = lz4_follow(n1, n2);
-        const uint32_t n4 = lz4_follow(n1, n3);
+        const uint32_t n2 = lane_follow(n1, n1);
+        const uint32_t n3 = lane_follow(n1, n2);
+        const uint32_t n4 = lane_follow(n1, n3);
         const uint64_t m4 = lz4_bit(l) | lz4_bit(n1) | lz4_bit(n2) | lz4_bit(n3);
-        const uint32_t n8 = lz4_follow(n4, n4);
-        const uint32_t m8h = lz4_pull((uint32_t)(m4 >> 32), n4), m8l = lz4_pull((uint32_t)m4, n4);
+        const uint32_t n8 = lane_follow(n4, n4);
+        const uint32_t m8h = lane_pull((uint32_t)(m4 >> 32), n4), m8l = lane_pull((uint32_t)m4, n4);
         const uint64_t m8 = m4 | (n4 < 64 ? (uint64_t)m8h << 32 | m8l : 0ull);
         // Links only lead forward, so eight steps of eight cover the window;
         // the bound is a second guard.

@@ -443,20 +443,23 @@ __device__ __forceinline__ int v2_index_short_repeats(Ring &in, uint32_t &pos, u
         const uint32_t h = (in.word(at_b >> 2) >> (8 * (at_b & 3))) & 0xff;
         const uint32_t w = ((h >> 3) & 7) + 1, cs = (h & 7) + 3;
         const uint32_t nxt = (h >> 6) == 0 && at_b + 1 + w <= end ? l + 1 + w : 128 + l;
-        // Fast path: the chain walked with one lane read per run carrying
-        // both the link and the run's value count; a window that holds no
-        // range start and stays inside the output needs nothing else.
+        // Fast path: a window that holds no range start and stays inside the
+        // output needs only the chain's end and its value count.  Each lane
+        // gathers, by link doubling, where its chain is after 8 runs (or
+        // where it ended) and how many values those runs hold, so the walk
+        // reads two lanes per 8 runs.
         {
-            const uint32_t link = nxt < 128 ? nxt | (cs << 8) : nxt;
+            const uint32_t c1 = nxt < 128 ? cs : 0u;
+            const uint32_t n2 = lane_follow(nxt, nxt), g1 = lane_pull(c1, nxt);
+            const uint32_t c2 = c1 + (nxt < 64 ? g1 : 0u);
+            const uint32_t n4 = lane_follow(n2, n2), g2 = lane_pull(c2, n2);
+            const uint32_t c4 = c2 + (n2 < 64 ? g2 : 0u);
+            const uint32_t n8 = lane_follow(n4, n4), g4 = lane_pull(c4, n4);
+            const uint32_t c8 = c4 + (n4 < 64 ? g4 : 0u);
             uint32_t t = 0, acc = nv;
-            for (;;) {
-                uint32_t v = readlane(link, t);
-                t = v & 0xff;
-                acc += v >> 8;
-                if (t >= kWave) break;
-                v = readlane(link, t);
-                t = v & 0xff;
-                acc += v >> 8;
+            for (uint32_t step = 0; step < 64; step++) {  // links only lead forward
+                acc += readlane(c8, t);
+                t = readlane(n8, t);
                 if (t >= kWave) break;
             }
             if (acc <= cap && (j >= kV2Ranges || v2_threshold(cap, j) >= acc)) {

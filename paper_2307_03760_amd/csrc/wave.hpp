@@ -33,6 +33,21 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, uint32_t l) {
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+// Value of v in lane `from` (its low 6 bits), for every lane at once.  A
+// lane permute reads 0 from a lane that is switched off, so call this with
+// every lane on and select afterwards.
+__device__ __forceinline__ uint32_t lane_pull(uint32_t v, uint32_t from) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)((from & 63) << 2), (int)v);
+}
+
+// One doubling step over a table of links: a lane whose link `at` points at
+// a lane (below 64) takes that lane's entry of v; a link at 64 or beyond is
+// an end and stays as it is.
+__device__ __forceinline__ uint32_t lane_follow(uint32_t v, uint32_t at) {
+    const uint32_t r = lane_pull(v, at);
+    return at < 64 ? r : at;
+}
+
 // Number of set bits of m in lanes below this one.
 __device__ __forceinline__ uint32_t count_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
