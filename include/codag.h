@@ -265,10 +265,13 @@ void codag_shutdown(void);
 enum {
     CODAG_ORDER_INDEX = 0,   /* chunk index order (plain atomic queue) */
     CODAG_ORDER_GIVEN = 1,   /* the caller's permutation (`order` argument) */
-    CODAG_ORDER_LEARNED = 2  /* longest predicted decode time first, predicted by
+    CODAG_ORDER_LEARNED = 2, /* longest predicted decode time first, predicted by
                                 the plan's cost model (see codag_sched_*); a
                                 plan whose model was never trained or set runs
                                 in index order */
+    CODAG_ORDER_CODEC = 3    /* chunks grouped by codec (every RLE v1 chunk, then
+                                every RLE v2 chunk, ...; any order within a
+                                codec), sorted on the device at each launch */
 };
 
 /*
@@ -276,13 +279,16 @@ enum {
  *   waves_per_cu      resident waves per CU in the persistent grid (default:
  *                     as many as the per-wave LDS allows, at most 16).
  *   waves_per_block   1, 2 or 4 (default 2).
- *   lit_table_bits    Deflate literal/length table bits; only 9 here.
+ *   lit_table_bits    Deflate literal/length table bits, 9 or 10 (default 9).
  *   history_kib       Deflate and LZ4 LDS output window, 4, 8 or 16 KiB
  *                     (default 4).
  *   order             CODAG_ORDER_* (default CODAG_ORDER_INDEX).
  *   use_graph         nonzero: capture the launch sequence (queue reset,
  *                     scheduling steps, decode) in a hipGraph once per set of
  *                     arguments and replay it.
+ *   chunks_per_claim  queue positions a wave takes with one atomic add, 1..64
+ *                     (default 1): packs small chunks onto one claim at the
+ *                     cost of coarser balancing.
  */
 typedef struct codag_batch_opts {
     int waves_per_cu;
@@ -291,7 +297,8 @@ typedef struct codag_batch_opts {
     int history_kib;
     int order;
     int use_graph;
-    int reserved[10];
+    int chunks_per_claim;
+    int reserved[9];
 } codag_batch_opts;
 
 typedef struct codag_plan codag_plan;
@@ -332,14 +339,36 @@ int codag_decompress_batch(codag_plan *plan, const uint8_t *codecs, const uint8_
 
 /*
  * Time candidate launch configurations on these buffers (each `reps` times,
- * on `stream`, which is synchronized) and keep the fastest in the plan.
- * *best_ms (may be NULL) receives its time per launch.  The buffers are
- * decoded many times; the output is the same each time.
+ * on `stream`, which is synchronized) and keep the fastest in the plan:
+ * a coordinate search over history_kib, lit_table_bits, waves_per_block,
+ * chunks_per_claim, index against codec-grouped order (when the plan's
+ * order is CODAG_ORDER_INDEX) and waves_per_cu.  *best_ms (may be NULL)
+ * receives its time per launch.  The buffers are decoded many times; the
+ * output is the same each time.
+ *
+ * Results are cached for the process, keyed by the device's architecture
+ * name, its CU count and the chunk array's shape (each codec's share of the
+ * chunks in eighths, log2 of the mean output bytes per chunk and of the
+ * chunk count, the plan's order).  A call whose key is cached applies the
+ * cached configuration without timing anything and returns its time.
  */
 int codag_autotune(codag_plan *plan, const uint8_t *codecs, const uint8_t *comp_buf,
                    const uint64_t *chunk_offsets, uint8_t *out_buf, const uint64_t *out_offsets,
                    uint64_t n_chunks, const uint32_t *order, int reps, double *best_ms,
                    void *stream);
+
+/* The autotune cache as text (host memory), one line per entry:
+ * "key|history_kib|lit_table_bits|waves_per_block|chunks_per_claim|
+ * waves_per_cu|order|ms".  *len (may be NULL) receives the bytes needed,
+ * terminating NUL included; returns CODAG_E_INVALID_ARGUMENT when buf is
+ * NULL or shorter. */
+int codag_autotune_cache_save(char *buf, size_t cap, size_t *len);
+/* Merge entries in that format into the cache (an entry with a key already
+ * cached replaces it).  A malformed line, or a configuration the batched
+ * launch rejects, returns CODAG_E_INVALID_ARGUMENT and merges nothing. */
+int codag_autotune_cache_load(const char *text);
+/* Forget every cached entry. */
+void codag_autotune_cache_clear(void);
 
 /* ------------------------------------------------------------------------
  * Learned scheduling: a per-plan cost model.
@@ -382,6 +411,22 @@ int codag_sched_set_params(codag_plan *plan, const float *params, const float *n
 /* Copy the model out (either pointer may be NULL).  Returns
  * CODAG_E_INVALID_ARGUMENT if the plan has no model yet. */
 int codag_sched_get_params(const codag_plan *plan, float *params, float *norm);
+
+/*
+ * Serialize the model into host memory, CODAG_SCHED_BLOB_BYTES bytes: the
+ * 8 bytes "CODAGMLP", uint32 format version 1, uint32 feature, parameter and
+ * normalization counts (16, 5313, 34), the parameters and the normalization
+ * as little-endian floats (the codag_sched_set_params layout), then a
+ * uint64 FNV-1a hash of all bytes before it.  *len (may be NULL) receives
+ * CODAG_SCHED_BLOB_BYTES.  Returns CODAG_E_INVALID_ARGUMENT if buf is NULL
+ * or shorter, or the plan has no model.
+ */
+#define CODAG_SCHED_BLOB_BYTES (8 + 16 + 4 * (5313 + 34) + 8)
+int codag_sched_save(const codag_plan *plan, void *buf, size_t cap, size_t *len);
+/* Replace the model from such bytes (as codag_sched_set_params).  A wrong
+ * length, magic, version, count or hash, or a non-finite value, returns
+ * CODAG_E_INVALID_ARGUMENT and leaves the model as it was. */
+int codag_sched_load(codag_plan *plan, const void *buf, size_t len);
 
 /*
  * Fit the model to n samples: when seed is nonzero, first re-initialize the

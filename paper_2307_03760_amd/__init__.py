@@ -14,7 +14,8 @@ import threading
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcodag.so")
 
-ORDER_INDEX, ORDER_GIVEN, ORDER_LEARNED = 0, 1, 2
+ORDER_INDEX, ORDER_GIVEN, ORDER_LEARNED, ORDER_CODEC = 0, 1, 2, 3
+SCHED_BLOB_BYTES = 8 + 16 + 4 * (5313 + 34) + 8
 SCHED_FEATURES, SCHED_PARAMS, SCHED_NORM = 16, 5313, 34
 OK = 0
 RLE_V1, RLE_V2, DEFLATE, BYTE_RLE, LZ4 = 1, 2, 3, 4, 5
@@ -43,7 +44,7 @@ class BatchOpts(ctypes.Structure):
     _fields_ = [("waves_per_cu", ctypes.c_int), ("waves_per_block", ctypes.c_int),
                 ("lit_table_bits", ctypes.c_int), ("history_kib", ctypes.c_int),
                 ("order", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("reserved", ctypes.c_int * 10)]
+                ("chunks_per_claim", ctypes.c_int), ("reserved", ctypes.c_int * 9)]
 
 
 def lib():
@@ -86,6 +87,11 @@ def lib():
                 "codag_sched_grad": [vp, vp, vp, u64, fp, fp, vp],
                 "codag_sched_predict": [vp, vp, u64, vp, vp],
                 "codag_sched_order": [vp, vp, vp, vp, vp, u64, vp, vp],
+                "codag_sched_save": [vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+                "codag_sched_load": [vp, vp, ctypes.c_size_t],
+                "codag_autotune_cache_save": [ctypes.c_char_p, ctypes.c_size_t,
+                                              ctypes.POINTER(ctypes.c_size_t)],
+                "codag_autotune_cache_load": [ctypes.c_char_p],
             }
             for name, args in sigs.items():
                 fn = getattr(L, name)
@@ -93,6 +99,8 @@ def lib():
                 fn.restype = i32
             L.codag_plan_destroy.argtypes = [vp]
             L.codag_plan_destroy.restype = None
+            L.codag_autotune_cache_clear.argtypes = []
+            L.codag_autotune_cache_clear.restype = None
             _lib = L
     return _lib
 
@@ -204,6 +212,24 @@ def orc_decompress_stream(codec: int, framed, block_size: int, out, out_len, sta
         raise CodagError(rc, "codag_orc_decompress_stream")
 
 
+def autotune_cache_save() -> str:
+    """codag_autotune_cache_save: the process's autotune cache as text."""
+    n = ctypes.c_size_t(0)
+    lib().codag_autotune_cache_save(None, 0, ctypes.byref(n))
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib().codag_autotune_cache_save(buf, n.value, ctypes.byref(n)), "codag_autotune_cache_save")
+    return buf.value.decode()
+
+
+def autotune_cache_load(text: str) -> None:
+    """codag_autotune_cache_load."""
+    _check(lib().codag_autotune_cache_load(text.encode()), "codag_autotune_cache_load")
+
+
+def autotune_cache_clear() -> None:
+    lib().codag_autotune_cache_clear()
+
+
 def get_error(stream=None):
     """(status, first bad chunk or None) since the last call; synchronizes `stream`."""
     first = ctypes.c_uint64(0)
@@ -243,10 +269,12 @@ class Plan:
     the learned cost model.  Calls on one plan must not overlap in time.
     """
 
-    def __init__(self, *, waves_per_cu: int = 0, waves_per_block: int = 0,
-                 history_kib: int = 0, order: int = ORDER_INDEX, use_graph: bool = False):
+    def __init__(self, *, waves_per_cu: int = 0, waves_per_block: int = 0, lit_table_bits: int = 0,
+                 history_kib: int = 0, order: int = ORDER_INDEX, use_graph: bool = False,
+                 chunks_per_claim: int = 0):
         self._h = ctypes.c_void_p()
-        o = BatchOpts(waves_per_cu, waves_per_block, 0, history_kib, order, int(use_graph))
+        o = BatchOpts(waves_per_cu, waves_per_block, lit_table_bits, history_kib, order,
+                      int(use_graph), chunks_per_claim)
         _check(lib().codag_plan_create(ctypes.byref(self._h), ctypes.byref(o)), "codag_plan_create")
 
     def close(self) -> None:
@@ -327,6 +355,19 @@ class Plan:
         p, q = _floats(SCHED_PARAMS), _floats(SCHED_NORM)
         _check(lib().codag_sched_get_params(self._h, p, q), "codag_sched_get_params")
         return np.ctypeslib.as_array(p).copy(), np.ctypeslib.as_array(q).copy()
+
+    def save_model(self) -> bytes:
+        """codag_sched_save: the model as SCHED_BLOB_BYTES bytes."""
+        buf = ctypes.create_string_buffer(SCHED_BLOB_BYTES)
+        n = ctypes.c_size_t(0)
+        _check(lib().codag_sched_save(self._h, buf, SCHED_BLOB_BYTES, ctypes.byref(n)),
+               "codag_sched_save")
+        return buf.raw[: n.value]
+
+    def load_model(self, blob: bytes) -> None:
+        """codag_sched_load."""
+        b = bytes(blob)
+        _check(lib().codag_sched_load(self._h, ctypes.c_char_p(b), len(b)), "codag_sched_load")
 
     def _feat_target(self, feat, target):
         import torch

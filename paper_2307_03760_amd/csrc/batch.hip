@@ -11,8 +11,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "../../include/codag.h"
@@ -26,27 +28,33 @@ __global__ void reset_queue(uint32_t *head) {
     if (threadIdx.x == 0) *head = 0;
 }
 
-// One wave per queue position until the queue is empty.  Every store of a
-// per-chunk result is made by all lanes with the same value (a one-lane
-// branch inside this loop would make the compiler treat the loop as
-// divergent).
+// Each wave claims `claim` consecutive queue positions at a time (one
+// atomic add for several small chunks) until the queue is empty.  Every
+// store of a per-chunk result is made by all lanes with the same value (a
+// one-lane branch inside this loop would make the compiler treat the loop
+// as divergent).
 template <int TB, uint32_t H, int WPB>
 __global__ void __launch_bounds__(kWave * WPB)
     decode_batch(const uint8_t *codecs, const uint8_t *comp, const uint64_t *coff, uint8_t *out,
                  const uint64_t *ooff, uint32_t n, const uint32_t *order, uint32_t *head,
-                 int32_t *status, unsigned long long *err, uint64_t *ticks) {
+                 uint32_t claim, int32_t *status, unsigned long long *err, uint64_t *ticks) {
     __shared__ __align__(16) uint32_t s_ring[WPB][kRingLdsWords];
     __shared__ __align__(16) uint32_t s_land[WPB][kLandWords];
     __shared__ __align__(16) WaveScratch<CODAG_DEFLATE, TB, H> s_scratch[WPB];
     const uint32_t wave = uni(threadIdx.x / kWave);
+    uint32_t idx = 0, last = 0;
     for (;;) {
-        // Lane 0 adds one; the others add zero, so lane 0's old value is the
-        // claimed position whatever order the lanes' adds are applied in.
-        uint32_t idx = uni(atomicAdd(head, lane() == 0 ? 1u : 0u));
-        if (idx >= n) break;
-        uint32_t c = order ? uni(order[idx]) : idx;
+        if (idx == last) {
+            // Lane 0 adds; the others add zero, so lane 0's old value is the
+            // claimed position whatever order the lanes' adds are applied in.
+            idx = uni(atomicAdd(head, lane() == 0 ? claim : 0u));
+            if (idx >= n) break;
+            last = min(idx + claim, n);
+        }
+        const uint32_t q = idx++;
+        uint32_t c = order ? uni(order[q]) : q;
         if (c >= n) {  // not a permutation: report the queue position
-            atomicMin(err, (unsigned long long)error_key(idx, CODAG_E_INVALID_ARGUMENT));
+            atomicMin(err, (unsigned long long)error_key(q, CODAG_E_INVALID_ARGUMENT));
             continue;
         }
         uint32_t codec = uni((uint32_t)codecs[c]);
@@ -92,18 +100,22 @@ using namespace codag;
 namespace {
 
 constexpr uint32_t kLdsPerCu = 160 * 1024;
-constexpr int kBatchTB = 9;  // Deflate literal/length table bits in the batched kernel
+constexpr int kBatchTB = 9;  // default Deflate literal/length table bits in the batched kernel
 constexpr int kVgprWavesPerSimd = 5;  // the decoders use up to 92 VGPRs
 
-
-uint32_t lds_per_wave(int hist_kib) {
-    return hist_kib == 16  ? batch_lds_per_wave<kBatchTB, 16384>()
-           : hist_kib == 8 ? batch_lds_per_wave<kBatchTB, 8192>()
-                           : batch_lds_per_wave<kBatchTB, 4096>();
+template <int TB>
+uint32_t lds_per_wave_tb(int hist_kib) {
+    return hist_kib == 16  ? batch_lds_per_wave<TB, 16384>()
+           : hist_kib == 8 ? batch_lds_per_wave<TB, 8192>()
+                           : batch_lds_per_wave<TB, 4096>();
 }
 
-int max_waves_per_cu(int hist_kib, int wpb) {
-    int by_lds = (int)(kLdsPerCu / (lds_per_wave(hist_kib) * wpb)) * wpb;
+uint32_t lds_per_wave(int hist_kib, int tb) {
+    return tb == 10 ? lds_per_wave_tb<10>(hist_kib) : lds_per_wave_tb<9>(hist_kib);
+}
+
+int max_waves_per_cu(int hist_kib, int tb, int wpb) {
+    int by_lds = (int)(kLdsPerCu / (lds_per_wave(hist_kib, tb) * wpb)) * wpb;
     return std::max(wpb, std::min({by_lds, 4 * kVgprWavesPerSimd, 16}));
 }
 
@@ -127,22 +139,47 @@ int resolve_opts(const codag_batch_opts *in, codag_batch_opts *o) {
     if (r.history_kib == 0) r.history_kib = 4;
     if (r.waves_per_block != 1 && r.waves_per_block != 2 && r.waves_per_block != 4)
         return CODAG_E_INVALID_ARGUMENT;
-    if (r.lit_table_bits != kBatchTB) return CODAG_E_INVALID_ARGUMENT;
+    if (r.chunks_per_claim == 0) r.chunks_per_claim = 1;
+    if (r.lit_table_bits != 9 && r.lit_table_bits != 10) return CODAG_E_INVALID_ARGUMENT;
     if (r.history_kib != 4 && r.history_kib != 8 && r.history_kib != 16) return CODAG_E_INVALID_ARGUMENT;
-    if (r.order < CODAG_ORDER_INDEX || r.order > CODAG_ORDER_LEARNED) return CODAG_E_INVALID_ARGUMENT;
+    if (r.order < CODAG_ORDER_INDEX || r.order > CODAG_ORDER_CODEC) return CODAG_E_INVALID_ARGUMENT;
+    if (r.chunks_per_claim < 1 || r.chunks_per_claim > 64) return CODAG_E_INVALID_ARGUMENT;
     if (r.waves_per_cu < 0 || r.waves_per_cu > 64) return CODAG_E_INVALID_ARGUMENT;
-    if (r.waves_per_cu == 0) r.waves_per_cu = max_waves_per_cu(r.history_kib, r.waves_per_block);
+    if (r.waves_per_cu == 0)
+        r.waves_per_cu = max_waves_per_cu(r.history_kib, r.lit_table_bits, r.waves_per_block);
     *o = r;
     return CODAG_OK;
 }
 
-template <uint32_t H, int WPB>
+template <int TB, uint32_t H, int WPB>
 void launch_decode(codag_plan *p, const BatchArgs &a, const uint32_t *order, unsigned long long *err,
                    hipStream_t s) {
     uint32_t blocks = (uint32_t)std::max<int64_t>(1, ((int64_t)p->num_cus * p->opts.waves_per_cu) / WPB);
-    hipLaunchKernelGGL((decode_batch<kBatchTB, H, WPB>), dim3(blocks), dim3(kWave * WPB), 0, s, a.codecs,
-                       a.comp, a.coff, a.out, a.ooff, (uint32_t)a.n, order, p->head, a.status, err,
-                       a.ticks);
+    hipLaunchKernelGGL((decode_batch<TB, H, WPB>), dim3(blocks), dim3(kWave * WPB), 0, s, a.codecs,
+                       a.comp, a.coff, a.out, a.ooff, (uint32_t)a.n, order, p->head,
+                       (uint32_t)p->opts.chunks_per_claim, a.status, err, a.ticks);
+}
+
+template <int TB>
+void launch_decode_tb(codag_plan *p, const BatchArgs &a, const uint32_t *order,
+                      unsigned long long *err, hipStream_t s) {
+    const int h = p->opts.history_kib;
+    switch (p->opts.waves_per_block) {
+        case 1:
+            h == 16 ? launch_decode<TB, 16384, 1>(p, a, order, err, s)
+            : h == 8 ? launch_decode<TB, 8192, 1>(p, a, order, err, s)
+                     : launch_decode<TB, 4096, 1>(p, a, order, err, s);
+            break;
+        case 4:
+            h == 16 ? launch_decode<TB, 16384, 4>(p, a, order, err, s)
+            : h == 8 ? launch_decode<TB, 8192, 4>(p, a, order, err, s)
+                     : launch_decode<TB, 4096, 4>(p, a, order, err, s);
+            break;
+        default:
+            h == 16 ? launch_decode<TB, 16384, 2>(p, a, order, err, s)
+            : h == 8 ? launch_decode<TB, 8192, 2>(p, a, order, err, s)
+                     : launch_decode<TB, 4096, 2>(p, a, order, err, s);
+    }
 }
 
 // Enqueue the whole sequence on s.
@@ -156,24 +193,15 @@ int enqueue(codag_plan *p, const BatchArgs &a, unsigned long long *err, hipStrea
                                      p->sched.order, s);
         if (st) return st;
         order = p->sched.order;
+    } else if (p->opts.order == CODAG_ORDER_CODEC) {
+        int st = sched_enqueue_codec_order(&p->sched, a.codecs, (uint32_t)a.n, p->sched.order, s);
+        if (st) return st;
+        order = p->sched.order;
     }
-    const int h = p->opts.history_kib;
-    switch (p->opts.waves_per_block) {
-        case 1:
-            h == 16 ? launch_decode<16384, 1>(p, a, order, err, s)
-            : h == 8 ? launch_decode<8192, 1>(p, a, order, err, s)
-                     : launch_decode<4096, 1>(p, a, order, err, s);
-            break;
-        case 4:
-            h == 16 ? launch_decode<16384, 4>(p, a, order, err, s)
-            : h == 8 ? launch_decode<8192, 4>(p, a, order, err, s)
-                     : launch_decode<4096, 4>(p, a, order, err, s);
-            break;
-        default:
-            h == 16 ? launch_decode<16384, 2>(p, a, order, err, s)
-            : h == 8 ? launch_decode<8192, 2>(p, a, order, err, s)
-                     : launch_decode<4096, 2>(p, a, order, err, s);
-    }
+    if (p->opts.lit_table_bits == 10)
+        launch_decode_tb<10>(p, a, order, err, s);
+    else
+        launch_decode_tb<9>(p, a, order, err, s);
     return hipGetLastError() == hipSuccess ? CODAG_OK : CODAG_E_HIP;
 }
 
@@ -182,7 +210,8 @@ int run_batch(codag_plan *p, const BatchArgs &a, hipStream_t s) {
     int st = device_state(&ds);
     if (st) return st;
     // The scheduler's per-chunk buffers are sized here, never during capture.
-    if (p->opts.order == CODAG_ORDER_LEARNED && p->sched.trained &&
+    if (((p->opts.order == CODAG_ORDER_LEARNED && p->sched.trained) ||
+         p->opts.order == CODAG_ORDER_CODEC) &&
         (st = sched_reserve(&p->sched, (uint32_t)a.n)))
         return st;
     if (!p->opts.use_graph) return enqueue(p, a, ds->err, s);
@@ -206,6 +235,55 @@ int run_batch(codag_plan *p, const BatchArgs &a, hipStream_t s) {
         p->have_key = true;
     }
     return hipGraphLaunch(p->exec, s) == hipSuccess ? CODAG_OK : CODAG_E_HIP;
+}
+
+// Autotune results kept for the process, keyed by the device's
+// architecture, its CU count and the shape of the chunk array: the share of
+// each codec in eighths, log2 of the mean output bytes per chunk and of the
+// chunk count, and the plan's queue order.
+struct TuneEntry {
+    std::string key;
+    codag_batch_opts opts;
+    double ms;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+int tune_key(codag_plan *p, const uint8_t *codecs, const uint64_t *ooff, uint64_t n, hipStream_t s,
+             std::string &key) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) return CODAG_E_HIP;
+    std::vector<uint8_t> c(n);
+    uint64_t o[2] = {0, 0};
+    if (hipMemcpyAsync(c.data(), codecs, n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&o[0], ooff, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&o[1], ooff + n, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return CODAG_E_HIP;
+    uint64_t count[6] = {0, 0, 0, 0, 0, 0};
+    for (uint8_t v : c) count[v <= CODAG_LZ4 ? v : 0]++;
+    const uint64_t mean = o[1] > o[0] ? (o[1] - o[0]) / n : 0;
+    char buf[384];
+    int len = std::snprintf(buf, sizeof(buf), "%s cus=%d mix=", prop.gcnArchName, p->num_cus);
+    for (int k = 0; k < 6; k++)
+        len += std::snprintf(buf + len, sizeof(buf) - len, "%s%d", k ? "," : "",
+                             (int)((8 * count[k] + n / 2) / n));
+    std::snprintf(buf + len, sizeof(buf) - len, " out=2^%d n=2^%d order=%d",
+                  mean ? 63 - __builtin_clzll(mean) : 0, 63 - __builtin_clzll(n), p->opts.order);
+    key = buf;
+    for (char &ch : key)
+        if (ch == '|' || ch == '\n') ch = '_';
+    return CODAG_OK;
+}
+
+// The tuned knobs of a cached configuration, laid over the plan's own.
+void apply_tuned(const codag_batch_opts &t, codag_batch_opts *o) {
+    o->history_kib = t.history_kib;
+    o->lit_table_bits = t.lit_table_bits;
+    o->waves_per_block = t.waves_per_block;
+    o->chunks_per_claim = t.chunks_per_claim;
+    o->waves_per_cu = t.waves_per_cu;
+    if (o->order == CODAG_ORDER_INDEX) o->order = t.order;
 }
 
 int check_args(codag_plan *plan, const uint8_t *codecs, const uint8_t *comp, const uint64_t *coff,
@@ -301,17 +379,32 @@ int codag_autotune(codag_plan *plan, const uint8_t *codecs, const uint8_t *comp_
     int st = check_args(plan, codecs, comp_buf, chunk_offsets, out_buf, out_offsets, n_chunks, order);
     if (st) return st;
     if (reps < 1 || reps > 1000) return CODAG_E_INVALID_ARGUMENT;
+    if (n_chunks == 0) return CODAG_OK;
     std::lock_guard<std::mutex> lock(plan->mu);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const codag_batch_opts base = plan->opts;
+    std::string key;
+    if ((st = tune_key(plan, codecs, out_offsets, n_chunks, s, key))) return st;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        for (const TuneEntry &e : g_tune) {
+            if (e.key != key) continue;
+            codag_batch_opts o = base, r;
+            apply_tuned(e.opts, &o);
+            if (resolve_opts(&o, &r)) break;  // stale entry: tune again
+            r.use_graph = base.use_graph;
+            plan->opts = r;
+            drop_graph(plan);
+            if (best_ms) *best_ms = e.ms;
+            return CODAG_OK;
+        }
+    }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return CODAG_E_HIP;
     if (hipEventCreate(&e1) != hipSuccess) {
         (void)hipEventDestroy(e0);
         return CODAG_E_HIP;
     }
-    BatchArgs a{codecs, comp_buf, chunk_offsets, out_buf, out_offsets, n_chunks, nullptr,
-                base.order == CODAG_ORDER_GIVEN ? order : nullptr, nullptr};
     double best = 1e30;
     codag_batch_opts best_opts = base;
     auto trial = [&](codag_batch_opts o) -> int {
@@ -319,6 +412,8 @@ int codag_autotune(codag_plan *plan, const uint8_t *codecs, const uint8_t *comp_
         if (resolve_opts(&o, &r)) return CODAG_OK;
         plan->opts = r;
         plan->opts.use_graph = 0;
+        BatchArgs a{codecs, comp_buf, chunk_offsets, out_buf, out_offsets, n_chunks, nullptr,
+                    r.order == CODAG_ORDER_GIVEN ? order : nullptr, nullptr};
         int rc = run_batch(plan, a, s);  // warm-up
         if (rc) return rc;
         std::vector<float> t;
@@ -341,13 +436,23 @@ int codag_autotune(codag_plan *plan, const uint8_t *codecs, const uint8_t *comp_
         }
         return CODAG_OK;
     };
-    // Coordinate search: window size, then waves per workgroup, then the
-    // number of resident waves per CU.
+    // Coordinate search: window size, Deflate table bits, waves per
+    // workgroup, chunks per queue claim, codec-grouped against index order
+    // (when the plan's order is the index order), then the number of
+    // resident waves per CU.
     for (int hist : {4, 8, 16}) {
+        if (st) break;
         codag_batch_opts o = base;
         o.history_kib = hist;
         o.waves_per_cu = 0;
-        if ((st = trial(o))) break;
+        st = trial(o);
+    }
+    for (int tb : {9, 10}) {
+        if (st) break;
+        codag_batch_opts o = best_opts;
+        o.lit_table_bits = tb;
+        o.waves_per_cu = 0;
+        st = trial(o);
     }
     for (int wpb : {1, 2, 4}) {
         if (st) break;
@@ -356,8 +461,25 @@ int codag_autotune(codag_plan *plan, const uint8_t *codecs, const uint8_t *comp_
         o.waves_per_cu = 0;
         st = trial(o);
     }
+    for (int claim : {1, 2, 4}) {
+        if (st) break;
+        codag_batch_opts o = best_opts;
+        o.chunks_per_claim = claim;
+        o.waves_per_cu = 0;
+        st = trial(o);
+    }
+    if (base.order == CODAG_ORDER_INDEX) {
+        for (int ord : {CODAG_ORDER_INDEX, CODAG_ORDER_CODEC}) {
+            if (st) break;
+            codag_batch_opts o = best_opts;
+            o.order = ord;
+            o.waves_per_cu = 0;
+            st = trial(o);
+        }
+    }
     if (!st) {
-        int top = max_waves_per_cu(best_opts.history_kib, best_opts.waves_per_block);
+        int top = max_waves_per_cu(best_opts.history_kib, best_opts.lit_table_bits,
+                                   best_opts.waves_per_block);
         for (int w = top - 2 * best_opts.waves_per_block; w >= std::max(4, top / 2) && !st;
              w -= 2 * best_opts.waves_per_block) {
             codag_batch_opts o = best_opts;
@@ -370,7 +492,69 @@ int codag_autotune(codag_plan *plan, const uint8_t *codecs, const uint8_t *comp_
     plan->opts = best_opts;
     drop_graph(plan);
     if (best_ms) *best_ms = best;
+    if (!st) {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune.push_back(TuneEntry{key, best_opts, best});
+    }
     return st;
+}
+
+int codag_autotune_cache_save(char *buf, size_t cap, size_t *len) {
+    std::string text;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        for (const TuneEntry &e : g_tune) {
+            char line[160];
+            std::snprintf(line, sizeof(line), "|%d|%d|%d|%d|%d|%d|%.6f\n", e.opts.history_kib,
+                          e.opts.lit_table_bits, e.opts.waves_per_block, e.opts.chunks_per_claim,
+                          e.opts.waves_per_cu, e.opts.order, e.ms);
+            text += e.key;
+            text += line;
+        }
+    }
+    if (len) *len = text.size() + 1;
+    if (!buf || cap < text.size() + 1) return CODAG_E_INVALID_ARGUMENT;
+    std::memcpy(buf, text.c_str(), text.size() + 1);
+    return CODAG_OK;
+}
+
+int codag_autotune_cache_load(const char *text) {
+    if (!text) return CODAG_E_INVALID_ARGUMENT;
+    std::vector<TuneEntry> add;
+    const char *p = text;
+    while (*p) {
+        const char *nl = std::strchr(p, '\n');
+        if (!nl) return CODAG_E_INVALID_ARGUMENT;
+        std::string line(p, nl);
+        p = nl + 1;
+        const size_t bar = line.find('|');
+        if (bar == 0 || bar == std::string::npos) return CODAG_E_INVALID_ARGUMENT;
+        TuneEntry e{};
+        e.key = line.substr(0, bar);
+        int nread = 0;
+        if (std::sscanf(line.c_str() + bar, "|%d|%d|%d|%d|%d|%d|%lf%n", &e.opts.history_kib,
+                        &e.opts.lit_table_bits, &e.opts.waves_per_block, &e.opts.chunks_per_claim,
+                        &e.opts.waves_per_cu, &e.opts.order, &e.ms, &nread) != 7 ||
+            (size_t)nread != line.size() - bar || !(e.ms >= 0))
+            return CODAG_E_INVALID_ARGUMENT;
+        codag_batch_opts r;
+        if (e.opts.waves_per_cu < 1 || resolve_opts(&e.opts, &r)) return CODAG_E_INVALID_ARGUMENT;
+        add.push_back(e);
+    }
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    for (TuneEntry &e : add) {
+        auto it = std::find_if(g_tune.begin(), g_tune.end(), [&](const TuneEntry &x) { return x.key == e.key; });
+        if (it != g_tune.end())
+            *it = e;
+        else
+            g_tune.push_back(e);
+    }
+    return CODAG_OK;
+}
+
+void codag_autotune_cache_clear(void) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune.clear();
 }
 
 }  // extern "C"

@@ -322,6 +322,15 @@ __global__ void __launch_bounds__(1024) sort_scan(uint32_t *hist) {
     }
 }
 
+// Codec-grouped order: the key is the chunk's codec byte.
+__global__ void sort_keys_codec(const uint8_t *codecs, uint32_t n, uint32_t *key, uint32_t *hist) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t k = codecs[i];
+    key[i] = k;
+    atomicAdd(&hist[k], 1u);
+}
+
 __global__ void sort_scatter(const uint32_t *key, uint32_t n, uint32_t *hist, uint32_t *order) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -512,6 +521,17 @@ int sched_reserve(SchedState *s, uint32_t n) {
     return CODAG_OK;
 }
 
+int sched_enqueue_codec_order(SchedState *s, const uint8_t *codecs, uint32_t n, uint32_t *order_out,
+                              hipStream_t st) {
+    if (n > s->cap) return CODAG_E_INVALID_ARGUMENT;
+    uint32_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(sort_clear, dim3(1), dim3(1024), 0, st, s->hist);
+    hipLaunchKernelGGL(sort_keys_codec, dim3(blocks), dim3(256), 0, st, codecs, n, s->key, s->hist);
+    hipLaunchKernelGGL(sort_scan, dim3(1), dim3(1024), 0, st, s->hist);
+    hipLaunchKernelGGL(sort_scatter, dim3(blocks), dim3(256), 0, st, s->key, n, s->hist, order_out);
+    return launched();
+}
+
 int sched_enqueue_order(SchedState *s, const uint8_t *codecs, const uint8_t *comp,
                         const uint64_t *coff, const uint64_t *ooff, uint32_t n,
                         uint32_t *order_out, hipStream_t st) {
@@ -568,6 +588,70 @@ int codag_sched_get_params(const codag_plan *plan, float *params, float *norm) {
         return CODAG_E_HIP;
     if (norm) std::memcpy(norm, plan->sched.norm_host, sizeof(plan->sched.norm_host));
     return CODAG_OK;
+}
+
+namespace {
+// Saved model layout: magic, format version, the three sizes, the packed
+// parameters and the normalization (little-endian floats), then a 64-bit
+// FNV-1a hash of everything before it.
+constexpr char kBlobMagic[8] = {'C', 'O', 'D', 'A', 'G', 'M', 'L', 'P'};
+constexpr uint32_t kBlobVersion = 1;
+constexpr size_t kBlobHeader = 8 + 4 * 4;
+static_assert(CODAG_SCHED_BLOB_BYTES == kBlobHeader + 4 * (kParams + kNorm) + 8, "blob size");
+
+uint64_t fnv1a64(const uint8_t *p, size_t n) {
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (size_t i = 0; i < n; i++) {
+        h ^= p[i];
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+}  // namespace
+
+int codag_sched_save(const codag_plan *plan, void *buf, size_t cap, size_t *len) {
+    int st = check_plan(plan);
+    if (st) return st;
+    if (len) *len = CODAG_SCHED_BLOB_BYTES;
+    if (!buf || cap < CODAG_SCHED_BLOB_BYTES) return CODAG_E_INVALID_ARGUMENT;
+    if (!plan->sched.trained) return CODAG_E_INVALID_ARGUMENT;
+    std::vector<float> params(kParams), norm(kNorm);
+    st = codag_sched_get_params(plan, params.data(), norm.data());
+    if (st) return st;
+    uint8_t *b = static_cast<uint8_t *>(buf);
+    const uint32_t hdr[4] = {kBlobVersion, (uint32_t)kFeatures, (uint32_t)kParams, (uint32_t)kNorm};
+    std::memcpy(b, kBlobMagic, 8);
+    std::memcpy(b + 8, hdr, sizeof(hdr));
+    std::memcpy(b + kBlobHeader, params.data(), 4 * kParams);
+    std::memcpy(b + kBlobHeader + 4 * kParams, norm.data(), 4 * kNorm);
+    const size_t body = kBlobHeader + 4 * (kParams + kNorm);
+    const uint64_t h = fnv1a64(b, body);
+    std::memcpy(b + body, &h, 8);
+    return CODAG_OK;
+}
+
+int codag_sched_load(codag_plan *plan, const void *buf, size_t len) {
+    int st = check_plan(plan);
+    if (st) return st;
+    if (!buf || len != CODAG_SCHED_BLOB_BYTES) return CODAG_E_INVALID_ARGUMENT;
+    const uint8_t *b = static_cast<const uint8_t *>(buf);
+    uint32_t hdr[4];
+    std::memcpy(hdr, b + 8, sizeof(hdr));
+    if (std::memcmp(b, kBlobMagic, 8) != 0 || hdr[0] != kBlobVersion || hdr[1] != (uint32_t)kFeatures ||
+        hdr[2] != (uint32_t)kParams || hdr[3] != (uint32_t)kNorm)
+        return CODAG_E_INVALID_ARGUMENT;
+    const size_t body = kBlobHeader + 4 * (kParams + kNorm);
+    uint64_t h;
+    std::memcpy(&h, b + body, 8);
+    if (h != fnv1a64(b, body)) return CODAG_E_INVALID_ARGUMENT;
+    std::vector<float> params(kParams), norm(kNorm);
+    std::memcpy(params.data(), b + kBlobHeader, 4 * kParams);
+    std::memcpy(norm.data(), b + kBlobHeader + 4 * kParams, 4 * kNorm);
+    for (float v : params)
+        if (!std::isfinite(v)) return CODAG_E_INVALID_ARGUMENT;
+    for (float v : norm)
+        if (!std::isfinite(v)) return CODAG_E_INVALID_ARGUMENT;
+    return codag_sched_set_params(plan, params.data(), norm.data());
 }
 
 int codag_sched_train(codag_plan *plan, const float *feat, const float *target, uint64_t n,

@@ -56,5 +56,9 @@ int sched_reserve(SchedState *s, uint32_t n);
 int sched_enqueue_order(SchedState *s, const uint8_t *codecs, const uint8_t *comp,
                         const uint64_t *coff, const uint64_t *ooff, uint32_t n,
                         uint32_t *order_out, hipStream_t st);
+// Enqueue a counting sort of n chunks (n <= s->cap) by codec byte: the
+// permutation lists every RLE v1 chunk, then every RLE v2 chunk, and so on.
+int sched_enqueue_codec_order(SchedState *s, const uint8_t *codecs, uint32_t n, uint32_t *order_out,
+                              hipStream_t st);
 
 }  // namespace codag

@@ -53,3 +53,38 @@ def test_binding_has_no_cpu_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(codag, "_lib", None)
     with pytest.raises(ImportError):
         codag.lib()
+
+
+def test_autotune_cache_text_round_trip():
+    """The autotune cache's text form is checked and merged on the host."""
+    import paper_2307_03760_amd as codag
+    if not os.path.exists(codag.LIB_PATH):
+        pytest.skip("library not built")
+    codag.autotune_cache_clear()
+    assert codag.autotune_cache_save() == ""
+    good = ("gfx950 cus=256 mix=3,3,2,0,0,0 out=2^16 n=2^14 order=0|8|10|2|1|12|0|41.500000\n"
+            "gfx950 cus=256 mix=0,0,0,8,0,0 out=2^16 n=2^14 order=2|4|9|1|4|16|2|40.250000\n")
+    codag.autotune_cache_load(good)
+    assert codag.autotune_cache_save() == good
+    # a key already cached is replaced, not duplicated
+    codag.autotune_cache_load(good.splitlines(True)[0].replace("|41.500000", "|39.000000"))
+    text = codag.autotune_cache_save()
+    assert text.count("\n") == 2 and "|39.000000" in text
+    bad = [
+        "no separators\n",
+        "|8|10|2|1|12|0|1.0\n",                       # empty key
+        "k|8|10|2|1|12|0\n",                          # a field missing
+        "k|8|11|2|1|12|0|1.0\n",                      # table bits the launch rejects
+        "k|5|9|2|1|12|0|1.0\n",                       # window size the launch rejects
+        "k|8|9|3|1|12|0|1.0\n",                       # waves per workgroup
+        "k|8|9|2|1|12|9|1.0\n",                       # unknown order
+        "k|8|9|2|1|12|0|1.0 trailing\n",
+        "k|8|9|2|1|12|0|1.0",                         # no newline
+    ]
+    for line in bad:
+        before = codag.autotune_cache_save()
+        with pytest.raises(codag.CodagError):
+            codag.autotune_cache_load(good.splitlines(True)[1] + line)
+        assert codag.autotune_cache_save() == before, line
+    codag.autotune_cache_clear()
+    assert codag.autotune_cache_save() == ""

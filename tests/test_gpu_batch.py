@@ -212,6 +212,57 @@ def test_autotune_keeps_a_valid_fast_config(dev, small):
     compare_chunks(*res, ref, ref_st, ch.out_offsets)
 
 
+@pytest.mark.parametrize("tb,claim,order", [(10, 1, 0), (9, 2, 0), (10, 4, 3), (9, 1, 3), (10, 3, 2)])
+def test_batch_table_bits_claims_codec_order(dev, small, tb, claim, order):
+    """Deflate table bits 10, several chunks per queue claim, and the
+    codec-grouped order (sorted on the device) decode like the oracle."""
+    import paper_2307_03760_amd as codag
+    ch, ref, ref_st = small
+    _say(f"batch tb={tb} claim={claim} order={order}")
+    plan = codag.Plan(lit_table_bits=tb, chunks_per_claim=claim, order=order, use_graph=True)
+    assert plan.opts["lit_table_bits"] == tb and plan.opts["chunks_per_claim"] == claim
+    (res, res2), _ = _run(plan, ch, dev, reps=2)
+    compare_chunks(*res, ref, ref_st, ch.out_offsets)
+    compare_chunks(*res2, ref, ref_st, ch.out_offsets)
+    plan.close()
+
+
+def test_autotune_cache_hit_and_text(dev, small):
+    """A second autotune of the same chunk array is served from the cache
+    (same configuration and time, no timing); the cache survives a text round
+    trip through clear and load; the cached configuration decodes correctly."""
+    import time
+    import torch
+    import paper_2307_03760_amd as codag
+    ch, ref, ref_st = small
+    codag.autotune_cache_clear()
+    codecs, comp, co, oo = batch_device_inputs(ch, dev)
+    out = torch.empty(ch.out_bytes, dtype=torch.uint8, device=dev)
+    p1 = codag.Plan()
+    best1 = p1.autotune(codecs, comp, co, out, oo, reps=2)
+    text = codag.autotune_cache_save()
+    assert text.count("\n") == 1 and text.split("|")[0].startswith("gfx")
+    p2 = codag.Plan()
+    t = time.perf_counter()
+    best2 = p2.autotune(codecs, comp, co, out, oo, reps=2)
+    cached_s = time.perf_counter() - t
+    assert best2 == pytest.approx(best1, rel=1e-5)
+    keys = ("history_kib", "lit_table_bits", "waves_per_block", "chunks_per_claim", "waves_per_cu", "order")
+    assert all(p1.opts[k] == p2.opts[k] for k in keys)
+    codag.autotune_cache_clear()
+    codag.autotune_cache_load(text)
+    assert codag.autotune_cache_save() == text
+    p3 = codag.Plan()
+    assert p3.autotune(codecs, comp, co, out, oo, reps=2) == pytest.approx(best1, rel=1e-5)
+    assert all(p1.opts[k] == p3.opts[k] for k in keys)
+    (res,), _ = _run(p3, ch, dev)
+    compare_chunks(*res, ref, ref_st, ch.out_offsets)
+    _say(f"autotune cached in {cached_s * 1e3:.1f} ms; opts {p3.opts}")
+    for p in (p1, p2, p3):
+        p.close()
+    codag.autotune_cache_clear()
+
+
 def test_batch_full_size(dev):
     """20,000 mixed chunks (about 2 GiB out) in the benchmark's launch
     (persistent, graph-captured): every chunk equals the oracle's decode

@@ -185,6 +185,54 @@ def test_training_is_deterministic_and_reduces_loss(dev):
     assert losses[-1] < 0.05 * losses[0], (losses[0], losses[-1])
 
 
+def test_model_save_load_round_trip(dev):
+    """codag_sched_save writes the documented layout; codag_sched_load into a
+    fresh plan gives back the same parameters and the same predictions; a
+    damaged, truncated or foreign blob is rejected and leaves the model as it
+    was."""
+    import struct
+    import torch
+    import paper_2307_03760_amd as codag
+    p, norm, feat, target = _random_model(12, 500)
+    a = codag.Plan()
+    with pytest.raises(codag.CodagError):
+        a.save_model()  # no model yet
+    a.set_params(p, norm)
+    blob = a.save_model()
+    assert len(blob) == codag.SCHED_BLOB_BYTES == 8 + 16 + 4 * (mlp.N_PARAMS + 34) + 8
+    assert blob[:8] == b"CODAGMLP" and struct.unpack("<4I", blob[8:24]) == (1, 16, mlp.N_PARAMS, 34)
+    assert np.array_equal(np.frombuffer(blob[24:24 + 4 * mlp.N_PARAMS], "<f4"), p)
+    assert np.array_equal(np.frombuffer(blob[24 + 4 * mlp.N_PARAMS:-8], "<f4"), norm)
+    h = 0xcbf29ce484222325
+    for byte in blob[:-8]:
+        h = ((h ^ byte) * 0x100000001b3) & (2 ** 64 - 1)
+    assert struct.unpack("<Q", blob[-8:])[0] == h
+    b = codag.Plan()
+    b.load_model(blob)
+    pb, nb = b.get_params()
+    assert np.array_equal(pb, p) and np.array_equal(nb, norm)
+    f_d = torch.from_numpy(feat).to(dev)
+    assert torch.equal(a.predict(f_d), b.predict(f_d))
+    other = codag.Plan()
+    other.set_params(p * 0.5, norm)
+    keep = other.get_params()
+    damaged = bytearray(blob)
+    damaged[100] ^= 1
+    nan = bytearray(blob)
+    nan[24:28] = struct.pack("<f", float("nan"))
+    h = 0xcbf29ce484222325
+    for byte in nan[:-8]:
+        h = ((h ^ byte) * 0x100000001b3) & (2 ** 64 - 1)
+    nan[-8:] = struct.pack("<Q", h)
+    for bad in (bytes(damaged), blob[:-1], b"X" + blob[1:], bytes(nan)):
+        with pytest.raises(codag.CodagError):
+            other.load_model(bad)
+        got = other.get_params()
+        assert np.array_equal(got[0], keep[0]) and np.array_equal(got[1], keep[1])
+    for pl in (a, b, other):
+        pl.close()
+
+
 def _spearman(a, b):
     ra, rb = np.argsort(np.argsort(a)), np.argsort(np.argsort(b))
     return float(np.corrcoef(ra, rb)[0, 1])
