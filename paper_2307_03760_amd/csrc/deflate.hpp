@@ -552,15 +552,17 @@ constexpr uint32_t kTokCopy = 0x8000u, kTokStop = 0x4000u, kTokOther = 0xc000u;
 // wave-uniform words s0..s4 (input words b/32 .. b/32 + 4); a length code
 // with its extra bits, the distance code and its extra bits take at most 36
 // bits.
-template <int TB, uint32_t H>
+template <int TB, uint32_t H, bool ALIGNED = false>
 __device__ __forceinline__ void lane_token(uint32_t s0, uint32_t s1, uint32_t s2, uint32_t s3,
                                            uint32_t s4, uint32_t b, const DeflateLds<TB, H> *lds,
                                            bool have_dist, uint32_t &info, uint32_t &dist) {
-    const uint32_t a = (b & 31) + lane();
+    // ALIGNED: b is a multiple of 32, so lane l starts in word l / 32 and
+    // s4 is not needed.
+    const uint32_t a = (ALIGNED ? 0u : (b & 31)) + lane();
     const uint32_t k = a >> 5, sh = a & 31;
-    const uint32_t wa = k == 0 ? s0 : k == 1 ? s1 : s2;
-    const uint32_t wb = k == 0 ? s1 : k == 1 ? s2 : s3;
-    const uint32_t wc = k == 0 ? s2 : k == 1 ? s3 : s4;
+    const uint32_t wa = ALIGNED ? (k ? s1 : s0) : k == 0 ? s0 : k == 1 ? s1 : s2;
+    const uint32_t wb = ALIGNED ? (k ? s2 : s1) : k == 0 ? s1 : k == 1 ? s2 : s3;
+    const uint32_t wc = ALIGNED ? (k ? s3 : s2) : k == 0 ? s2 : k == 1 ? s3 : s4;
     const uint64_t x = ((uint64_t)__builtin_amdgcn_alignbit(wc, wb, sh) << 32) |
                        __builtin_amdgcn_alignbit(wb, wa, sh);
     const uint32_t e = lds->lit[(uint32_t)x & ((1u << TB) - 1)];
@@ -584,78 +586,119 @@ __device__ __forceinline__ void lane_token(uint32_t s0, uint32_t s1, uint32_t s2
     }
 }
 
+// A copy's distance packed into its token word: distance - 1 (15 bits) in
+// bits 0-7 and 25-31, which a copy does not otherwise use.
+__device__ __forceinline__ uint32_t pack_token(uint32_t info, uint32_t dist) {
+    const uint32_t d = dist - 1;
+    return (info & kTokCopy) ? info | (d & 0xff) | ((d >> 8) << 25) : info;
+}
+__device__ __forceinline__ uint32_t token_dist(uint32_t w) { return ((w & 0xff) | ((w >> 25) << 8)) + 1; }
+__device__ __forceinline__ uint32_t token_len(uint32_t w) { return (w >> 16) & 511; }
+
+// The walk's view of a candidate: its bits plus, from bit 8, its output
+// length plus 12, so one add advances both the bit position within the
+// window (bits 0-7) and the batch budget (from bit 8); bit 31 marks a token
+// the batch cannot take.  The budget starts at kBudget0 and the batch is
+// full once it reaches 1024 (bit 18): at most 60 tokens, and at most 766
+// output bytes before the last token, so at most kBatchOut in all.
+constexpr uint32_t kWalkStop = 1u << 31, kBudget0 = 257, kBudgetFull = 1u << 18;
+constexpr uint32_t kWindowEnd = 1u << 6;  // bit position 64 or beyond
+__device__ __forceinline__ uint32_t walk_word(uint32_t info) {
+    return (info & kTokStop) ? kWalkStop : ((info >> 8) & 63) + ((((info >> 16) & 511) + 12) << 8);
+}
+
 template <int TB, uint32_t H, class Ring>
 __device__ __forceinline__ int inflate_batched(Ring &in, BitIn &bi, WindowOut<H> &o,
                                                DeflateLds<TB, H> *lds, bool have_dist,
                                                uint32_t len_tab, uint32_t dist_tab) {
     const uint32_t l = lane();
+    // Candidates are decoded for fixed 64-bit windows of the input (lane l:
+    // the token at bit 64 w + l).  The walk's tokens are staged, as packed
+    // token words, in the code-length scratch (free while symbols decode),
+    // one word per token of the batch.
+    uint32_t *stage = reinterpret_cast<uint32_t *>(lds->lens);
+    static_assert(sizeof(lds->lens) >= 4 * kWave, "staging space");
     uint32_t p = 8 * bi.next - bi.cnt;  // bit position of the next code
     // Input words [cend - 64, cend), one per lane, read from the ring once
-    // per 236 bytes or so; a window takes its five words out with readlane.
+    // per 240 bytes or so; a window takes its four words out with readlane.
     uint32_t cache = 0, cend = 0;
+    uint32_t wk = p >> 6;      // the window being walked (64-bit units)
+    uint32_t cur = 0, walk = 0;  // packed token and walk word of this lane's candidate in window wk
+    bool have = false;
     for (;;) {
         o.make_room(kBatchOut);
         // ---- collect a batch of tokens
-        uint32_t ntok = 0, bout = 0;
-        uint32_t tok = 0, tdist = 0;  // token k in lane k: length << 16 | literal, flag 0x8000 = copy
-        uint32_t stop = 0;            // 1 full, 2 end of block, 3 one symbol the slow way
-        const uint32_t total0 = o.pos;
-        uint32_t tpos = 0;  // token k's bit position, in lane k
+        uint32_t ntok = 0;
+        uint32_t stop = 0;  // 1 full, 2 end of block, 3 one symbol the slow way
+        const uint32_t total0 = o.pos, p0 = p;
+        uint32_t budget = kBudget0;
         do {
-            const uint32_t wi = p >> 5;
-            if (wi + 5 > cend) {
-                in.ensure(4 * (wi + 64) + 4);
-                cache = in.word(wi + l);
-                cend = wi + 64;
+            if (!have) {
+                const uint32_t wi = 2 * wk;
+                if (wi + 4 > cend || wi + 64 < cend) {
+                    in.ensure(4 * (wi + 64) + 4);
+                    cache = in.word(wi + l);
+                    cend = wi + 64;
+                }
+                const uint32_t c0 = wi + 64 - cend;
+                uint32_t info, dist;
+                lane_token<TB, H, true>(readlane(cache, c0), readlane(cache, c0 + 1),
+                                        readlane(cache, c0 + 2), readlane(cache, c0 + 3), 0u, 64 * wk,
+                                        lds, have_dist, info, dist);
+                cur = pack_token(info, dist);
+                walk = walk_word(info);
+                have = true;
             }
-            const uint32_t c0 = wi + 64 - cend;
-            uint32_t info, dist;
-            lane_token<TB, H>(readlane(cache, c0), readlane(cache, c0 + 1), readlane(cache, c0 + 2),
-                              readlane(cache, c0 + 3), readlane(cache, c0 + 4), p, lds, have_dist,
-                              info, dist);
-            // The walk only follows token starts and collects tokens; output
-            // bounds are checked lane-parallel once the batch is complete.
-            // Exits: a token the batch cannot take, the end of the window,
-            // a full batch (flags by integer arithmetic: values < 2^31).
-            // One exit test per token: the next token is read before the
-            // test (a harmless read when the window or batch is done).
-            uint32_t t = 0, full = 0, inf = readlane(info, 0);
-            if (!(inf & kTokStop)) {
-                for (;;) {
-                    const uint32_t d = readlane(dist, t);
-                    tok = l == ntok ? inf : tok;
-                    tdist = l == ntok ? d : tdist;
-                    tpos = l == ntok ? p + t : tpos;
-                    t += (inf >> 8) & 63;
-                    ntok++;
-                    bout += inf >> 16;
-                    full = ((t | ntok) >> 6) | (uint32_t)((int32_t)(kBatchOut - 258 - bout) >> 31);
-                    inf = readlane(info, t & 63);
-                    if (full | (inf & kTokStop)) break;
+            // The walk follows token starts only, one lane read and one add
+            // per token, until a token the batch cannot take, the end of the
+            // window or a full batch (output bounds are checked lane-parallel
+            // once the batch is complete).
+            uint32_t T = (p - 64 * wk) | (budget << 8);
+            uint32_t w = readlane(walk, T & 63);
+            uint64_t mark = 0;
+            while (!((w | T) & (kWalkStop | kWindowEnd | kBudgetFull))) {
+                mark |= 1ull << (T & 63);
+                T += w;
+                w = readlane(walk, T & 63);
+            }
+            // Stage this window's tokens in walk order.
+            if ((mark >> l) & 1) stage[ntok + count_below(mark)] = cur;
+            ntok += (uint32_t)__builtin_popcountll(mark);
+            budget = T >> 8;
+            const uint32_t t = T & 255;
+            p = 64 * wk + t;
+            if (t >= 64) {  // into the next window (a token ends at most 48 bits past this one)
+                wk++;
+                have = false;
+            } else if (budget >= 1024) {
+                stop = 1;  // batch full
+            } else {
+                const uint32_t inf = readlane(cur, t);
+                if (inf == (kTokStop | (inf & 0x3f00))) {  // end of block
+                    p += (inf >> 8) & 63;
+                    stop = 2;
+                } else {
+                    stop = 3;
                 }
             }
-            if (full) {
-                if (ntok == kWave || bout > kBatchOut - 258) stop = 1;  // batch full
-            } else if (inf == (kTokStop | (inf & 0x3f00))) {      // end of block
-                t += (inf >> 8) & 63;
-                stop = 2;
-            } else {
-                stop = 3;
-            }
-            p += t;
         } while (stop == 0);
+        uint32_t bout = budget - kBudget0 - 12 * ntok;
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t tok = l < ntok ? stage[l] : 0u;
+        const uint32_t tdist = (tok & kTokCopy) ? token_dist(tok) : 0u;
         // Output bounds, lane-parallel: the first token whose distance
         // reaches before the chunk or whose output would pass the end ends
         // the batch, and goes through the symbol-at-a-time path.
         if (ntok) {
-            const uint32_t vlen = l < ntok ? tok >> 16 : 0;
+            const uint32_t vlen = l < ntok ? token_len(tok) : 0;
             const uint32_t before = total0 + wave_inclusive_sum32(vlen) - vlen;
             const uint64_t badm = ballot(l < ntok && (tdist > before || before + vlen > o.cap));
             if (badm) {
                 const uint32_t j = (uint32_t)__builtin_ctzll(badm);
+                const uint32_t bits = l < j ? (tok >> 8) & 63 : 0u;
                 ntok = j;
                 bout = readlane(before, j) - total0;
-                p = readlane(tpos, j);
+                p = p0 + readlane(wave_inclusive_sum32(bits), 63);
                 stop = 3;
             }
         }
@@ -663,8 +706,8 @@ __device__ __forceinline__ int inflate_batched(Ring &in, BitIn &bi, WindowOut<H>
         // ---- write the batch
         if (ntok) {
             const bool valid = l < ntok;
-            const uint32_t len = valid ? tok >> 16 : 0;
-            const bool is_copy = valid && (tok & 0x8000u);
+            const uint32_t len = valid ? token_len(tok) : 0;
+            const bool is_copy = valid && (tok & kTokCopy);
             const uint32_t start = o.o0 + total0;  // first byte of the batch (window coordinates)
             const uint32_t dst = start + wave_inclusive_sum32(len) - len;
             if (valid && !is_copy) o.win[o.slot(dst)] = (uint8_t)tok;
@@ -739,6 +782,8 @@ __device__ __forceinline__ int inflate_batched(Ring &in, BitIn &bi, WindowOut<H>
         int st = inflate_symbols<TB, H, true>(in, bi, o, lds, have_dist, len_tab, dist_tab);
         if (st != kMore) return st;
         p = 8 * bi.next - bi.cnt;
+        wk = p >> 6;
+        have = 0;
     }
 }
 
