@@ -204,34 +204,43 @@ __global__ void __launch_bounds__(kIdxThreads)
                     __builtin_amdgcn_s_sleep(1);
             }
             helper_barrier(&s_sync[0], gen);
-            // Terminators before region byte x.
-            auto tcount = [&](uint32_t x) {
-                const uint32_t wd = buf[x >> 2];
-                return s_before[x >> 2] + __builtin_popcount(term_bits(wd) & ((1u << (x & 3)) - 1));
-            };
+            // Entries, four positions (one word) per thread.  A run is a
+            // header, a delta byte and a base varint from r = p + 2 to its
+            // terminator e; a literal list of 256 - h varints from r = p + 1
+            // ends at its last terminator.  Both take one count of the
+            // terminators before r, so every position is one path.
             uint32_t *ent = s_ent[t & 1];
-            for (uint32_t p = ht; p < kIdxStep; p += kWave * kIdxHelpers) {
-                const uint32_t hb = (buf[p >> 2] >> (8 * (p & 3))) & 0xff;
-                uint32_t e_out;
-                if (hb < 128) {
-                    // Run: header, delta byte, base varint from r to terminator e.
-                    const uint32_t r = p + 2, ti = tcount(r);
+            for (uint32_t q = ht; q < kIdxStep / 4; q += kWave * kIdxHelpers) {
+                const uint32_t w0 = buf[q], w1 = buf[q + 1];
+                const uint32_t sb0 = s_before[q], sb1 = s_before[q + 1];
+                const uint32_t tb0 = term_bits(w0), tb1 = term_bits(w1);
+                uint32_t e4[4];
+#pragma unroll
+                for (uint32_t i = 0; i < 4; i++) {
+                    const uint32_t p = 4 * q + i;
+                    const uint32_t hb = (w0 >> (8 * i)) & 0xff;
+                    const bool run = hb < 128;
+                    const uint32_t rr = i + 1 + (run ? 1u : 0u);  // r - 4q, 1..5
+                    const uint32_t r = 4 * q + rr, rb = rr & 3;
+                    const uint32_t tcnt = rr < 4 ? sb0 + __builtin_popcount(tb0 & ((1u << rb) - 1))
+                                                 : sb1 + __builtin_popcount(tb1 & ((1u << rb) - 1));
+                    const uint32_t cntl = 256 - hb;
+                    const uint32_t ti = tcnt + (run ? 0u : cntl - 1);
                     const uint32_t e = ti < total ? s_tpos[ti] : kIdxRegion;
-                    const uint32_t nb = e - r + 1;
-                    uint32_t code = kEntOk;
-                    if (W + r > end) code = kEntTruncated;
-                    else if (nb > 10 || (nb == 10 && ((buf[e >> 2] >> (8 * (e & 3))) & 0xff) > 1))
-                        code = kEntCorrupt;
-                    else if (W + e >= end) code = kEntTruncated;
-                    e_out = make_ent(code == kEntOk ? e + 1 - p : 0, hb + 3, code);
-                } else {
-                    // Literal list of 256 - hb varints: ends at its last terminator.
-                    const uint32_t cntl = 256 - hb, ti = tcount(p + 1) + cntl - 1;
-                    const uint32_t e = ti < total ? s_tpos[ti] : kIdxRegion;
-                    const bool open = e >= kIdxRegion || W + e >= end;
-                    e_out = make_ent(open ? 0 : e + 1 - p, cntl, open ? kEntOpen : kEntOk);
+                    if (run) {
+                        const uint32_t nb = e - r + 1;
+                        uint32_t code = kEntOk;
+                        if (W + r > end) code = kEntTruncated;
+                        else if (nb > 10 || (nb == 10 && ((buf[e >> 2] >> (8 * (e & 3))) & 0xff) > 1))
+                            code = kEntCorrupt;
+                        else if (W + e >= end) code = kEntTruncated;
+                        e4[i] = make_ent(code == kEntOk ? e + 1 - p : 0, hb + 3, code);
+                    } else {
+                        const bool open = e >= kIdxRegion || W + e >= end;
+                        e4[i] = make_ent(open ? 0 : e + 1 - p, cntl, open ? kEntOpen : kEntOk);
+                    }
                 }
-                ent[p] = e_out;
+                reinterpret_cast<uint4 *>(ent)[q] = make_uint4(e4[0], e4[1], e4[2], e4[3]);
             }
             helper_barrier(&s_sync[0], gen);
             if (h == 0 && l == 0) lds_store_release(&s_sync[1], t + 1);  // window t ready
@@ -254,7 +263,19 @@ __global__ void __launch_bounds__(kIdxThreads)
         // never passes a whole window, but an empty chunk starts past 0).
         if (nv < cap && pos < end && pos < W + kIdxStep) wait_at_least(&s_sync[1], t + 1);
         const uint32_t *ent = s_ent[t & 1];
+        const uint32_t lim = min(end, W + kIdxStep);
         while (true) {
+            // Fast path, scalar state only: groups that are valid, fit the
+            // output and start no range (the checks below, all passing).
+            const uint32_t fastlim = uni(j < kSplitWaves ? min(next, cap) : cap);
+            while (pos < lim && nv < fastlim) {
+                const uint32_t e = uni(ent[pos - W]);
+                const uint32_t len = (e >> 13) & 0xff;
+                if ((e >> 21) != kEntOk || nv + len > cap) break;
+                nv += len;
+                k++;
+                pos += e & 0x1fff;
+            }
             if (nv >= cap) {
                 done = true;
                 break;
@@ -285,7 +306,7 @@ __global__ void __launch_bounds__(kIdxThreads)
                 rpos = l == j ? gp : rpos;
                 rnv = l == j ? gn : rnv;
                 j++;
-                next = cap * j / kSplitWaves;  // cap < 2^28
+                next = uni(cap * j / kSplitWaves);  // cap < 2^28
             }
             k++;
             if (code == kEntOpen) {
