@@ -114,6 +114,7 @@ __global__ void __launch_bounds__(kIdxThreads)
     const uint8_t *gbase = chunk - skip;  // positions are relative to the 16-byte hull
     const uint32_t end = skip + in_len, cap = out_len / 8;
     if (tid < 4) s_sync[tid] = 0;
+    if (tid == 0) s_stop = 0;
     __syncthreads();
 
     if (wave != 0) {
@@ -132,33 +133,34 @@ __global__ void __launch_bounds__(kIdxThreads)
             }
         };
         issue(0);
+        wait_vm();
+        helper_barrier(&s_sync[0], gen);  // window 0's region has landed
         for (uint32_t t = 0; t * kIdxStep < end; t++) {
             const uint32_t W = t * kIdxStep;
             uint32_t *buf = s_buf[t & 1];
-            wait_vm();
-            // One helper samples the walker's flag before the barrier, so
-            // every helper takes the same decision after it.
-            if (h == 0 && l == 0) s_stop = lds_load_acquire(&s_sync[3]);
-            helper_barrier(&s_sync[0], gen);  // the region has landed
+            // s_stop was sampled before the barrier that ended the previous
+            // window, so every helper takes the same decision here.
             if (s_stop) break;
-            // Bytes past the end of the chunk read as zero (terminators).
-            for (uint32_t q = ht; q < kIdxPieces; q += kWave * kIdxHelpers) {
-                const uint32_t at = W + 16 * q;
-                if (at + 16 > end) {
-                    uint4 v = reinterpret_cast<uint4 *>(buf)[q];
-                    const uint32_t valid = at < end ? end - at : 0;
-                    uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                    for (int i = 0; i < 4; i++) {
-                        const int keep = (int)valid - 4 * i;
-                        w[i] &= keep >= 4 ? 0xffffffffu : keep <= 0 ? 0u : ((1u << (8 * keep)) - 1);
-                    }
-                    reinterpret_cast<uint4 *>(buf)[q] = make_uint4(w[0], w[1], w[2], w[3]);
-                }
-            }
             // The other buffer held window t - 1, whose entries are done.
             if (W + kIdxStep < end) issue(t + 1);
-            helper_barrier(&s_sync[0], gen);
+            // Bytes past the end of the chunk read as zero (terminators).
+            if (W + kIdxRegion > end) {
+                for (uint32_t q = ht; q < kIdxPieces; q += kWave * kIdxHelpers) {
+                    const uint32_t at = W + 16 * q;
+                    if (at + 16 > end) {
+                        uint4 v = reinterpret_cast<uint4 *>(buf)[q];
+                        const uint32_t valid = at < end ? end - at : 0;
+                        uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                        for (int i = 0; i < 4; i++) {
+                            const int keep = (int)valid - 4 * i;
+                            w[i] &= keep >= 4 ? 0xffffffffu : keep <= 0 ? 0u : ((1u << (8 * keep)) - 1);
+                        }
+                        reinterpret_cast<uint4 *>(buf)[q] = make_uint4(w[0], w[1], w[2], w[3]);
+                    }
+                }
+                helper_barrier(&s_sync[0], gen);
+            }
             // Terminator counts: helper thread ht takes region bytes
             // [16 ht, 16 ht + 16).
             uint32_t tb[4] = {0, 0, 0, 0};
@@ -242,6 +244,11 @@ __global__ void __launch_bounds__(kIdxThreads)
                 }
                 reinterpret_cast<uint4 *>(ent)[q] = make_uint4(e4[0], e4[1], e4[2], e4[3]);
             }
+            // One barrier ends the window: its entries are complete, the next
+            // window's region (issued above) has landed, and every helper
+            // sees the same walk-done sample.
+            wait_vm();
+            if (h == 0 && l == 0) s_stop = lds_load_acquire(&s_sync[3]);
             helper_barrier(&s_sync[0], gen);
             if (h == 0 && l == 0) lds_store_release(&s_sync[1], t + 1);  // window t ready
         }
