@@ -330,7 +330,7 @@ def launch_description(codec: int, n_chunks: int) -> str:
                 "chunk into 8 ranges) + rle_v2_ranges (one wave per range) + split_finish")
     if codec == 1 and n_chunks <= 256:
         return ("group-parallel: rle_v1_index (a 16-wave workgroup per chunk finds group starts "
-                "and cuts 16 ranges) + rle_v1_groups (one wave per range) + split_finish")
+                "and cuts 32 ranges) + rle_v1_groups (one wave per range) + split_finish")
     if codec == 3:
         return "decode_plain<DEFLATE>: one wave64 per chunk, 1 wave per workgroup, 4 KiB LDS window"
     if codec == 5:

@@ -74,9 +74,9 @@ enum {
  *                     Group-parallel: an index pass finds where the groups
  *                     (RLE v1 runs and literal lists; RLE v2 runs) start,
  *                     without decoding values, and cuts them into ranges of
- *                     about equal output -- 16 per RLE v1 chunk, 8 per RLE
+ *                     about equal output -- 32 per RLE v1 chunk, 8 per RLE
  *                     v2 chunk -- then one wave per range decodes it.  The
- *                     path takes its workspace (272 bytes per RLE v1 chunk,
+ *                     path takes its workspace (528 bytes per RLE v1 chunk,
  *                     96 per RLE v2 chunk) from the stream-ordered allocator
  *                     (hipMallocAsync) on `stream`.  Ignored for Deflate
  *                     and LZ4.
@@ -185,7 +185,7 @@ int codag_decompress_ex(int codec, const uint8_t *comp_buf, const uint64_t *chun
  * any count with group_parallel = 2), take it from a static per-device
  * array of CODAG_NOALLOC_SCRATCH_BYTES bytes that the library holds on every
  * device it runs on until the process ends; a launch needing more than that
- * (group_parallel = 2 with more than 722 RLE v1 or 2048 RLE v2 chunks)
+ * (group_parallel = 2 with more than 372 RLE v1 or 2048 RLE v2 chunks)
  * returns CODAG_E_INVALID_ARGUMENT.  Every call on one device shares that
  * array: calls that overlap in time on one device (on different streams or
  * threads) race and must not be made.

@@ -33,8 +33,8 @@ int launch_rle_v1_split(const uint8_t *comp, const uint64_t *coff, uint8_t *out,
                         hipStream_t s, void *workspace);
 size_t rle_v1_split_workspace(uint32_t n);
 constexpr uint64_t kSplitMaxChunks = 256;
-// Per chunk: 16 range records of 16 bytes and two 8-byte error keys.
-constexpr size_t kSplitWorkspacePerChunk = 16 * 16 + 2 * 8;
+// Per chunk: 32 range records of 16 bytes and two 8-byte error keys.
+constexpr size_t kSplitWorkspacePerChunk = 32 * 16 + 2 * 8;
 
 // Group-parallel RLE v2 (index pass, one decoding wave per range, status
 // pass), the same way; workspace rle_v2_split_workspace(n) bytes.

@@ -18,7 +18,7 @@
 
 namespace codag {
 
-constexpr uint32_t kSplitWaves = 16;  // decoding waves per chunk
+constexpr uint32_t kSplitWaves = 32;  // decoding waves per chunk
 constexpr int kSplitWpb = 4;          // decode pass: waves per block
 
 // With a few dozen waves on the chip each wave waits on every fetch it
@@ -313,7 +313,7 @@ __global__ void __launch_bounds__(kIdxThreads)
                 rpos = l == j ? gp : rpos;
                 rnv = l == j ? gn : rnv;
                 j++;
-                next = uni(cap * j / kSplitWaves);  // cap < 2^28
+                next = uni((uint32_t)((uint64_t)cap * j / kSplitWaves));
             }
             k++;
             if (code == kEntOpen) {

@@ -89,10 +89,10 @@ def test_noalloc_matches_ex(dev, case):
         codag.get_error()
 
 
-@pytest.mark.parametrize("codec,over", [(oracle.RLE_V1, 723), (oracle.RLE_V2, 2049)])
+@pytest.mark.parametrize("codec,over", [(oracle.RLE_V1, 373), (oracle.RLE_V2, 2049)])
 def test_noalloc_rejects_workspace_beyond_scratch(dev, codec, over):
     """Forced group-parallel launches whose workspace exceeds the scratch
-    array (RLE v1: 272 bytes per chunk, RLE v2: 96, of 196,608) are refused;
+    array (RLE v1: 528 bytes per chunk, RLE v2: 96, of 196,608) are refused;
     the allocating entry point takes them, and with the default path choice
     the no-allocation entry point decodes them one wave per chunk."""
     import paper_2307_03760_amd as codag
