@@ -23,8 +23,8 @@ template <int Codec, int TB, uint32_t H, int WPB>
 __global__ void __launch_bounds__(kWave * WPB)
     decode_plain(const uint8_t *comp, const uint64_t *coff, uint8_t *out, const uint64_t *ooff,
                  uint32_t n, int32_t *status, unsigned long long *err, uint64_t *ticks) {
-    __shared__ __align__(16) uint32_t s_ring[WPB][kRingLdsWords];
-    __shared__ __align__(16) uint32_t s_land[WPB][kLandWords];
+    __shared__ __align__(16) uint32_t s_ring[WPB][ring_lds_words<Codec>()];
+    __shared__ __align__(16) uint32_t s_land[WPB][land_lds_words<Codec>()];
     __shared__ __align__(16) WaveScratch<Codec, TB, H> s_scratch[WPB];
     uint32_t wave = uni(threadIdx.x / kWave);
     uint32_t c = blockIdx.x * WPB + wave;

@@ -30,6 +30,33 @@ __device__ __forceinline__ uint64_t error_key(uint64_t chunk, int st) {
     return (chunk << 4) | (uint64_t)(uint32_t)(-st);
 }
 
+// The input ring each codec decodes from.  Deflate and LZ4 spend tens of
+// microseconds per input kilobyte and are held to fewer waves per CU by
+// their LDS, so they fetch synchronously into a 1 KiB ring; the RLE decoders
+// read input fast and keep the fetch-ahead ring.
+template <int Codec>
+struct RingOf {
+    using T = InRing;
+};
+template <>
+struct RingOf<CODAG_DEFLATE> {
+    using T = DirectRing<512>;
+};
+template <>
+struct RingOf<CODAG_LZ4> {
+    using T = DirectRing<512>;
+};
+// LDS words of a codec's ring and landing buffer (at least one word each,
+// for the kernels' arrays).
+template <int Codec>
+constexpr uint32_t ring_lds_words() {
+    return RingOf<Codec>::T::kLdsWords;
+}
+template <int Codec>
+constexpr uint32_t land_lds_words() {
+    return RingOf<Codec>::T::kLand ? RingOf<Codec>::T::kLand : 1u;
+}
+
 // Decodes chunk c with the calling wave; returns its status.  E is the
 // element type of the RLE codecs (int64 unless a typed launch says
 // otherwise).
@@ -42,7 +69,7 @@ __device__ __forceinline__ int decode_one(const uint8_t *comp, const uint64_t *c
     if ((((i1 - i0) | (o1 - o0)) >> 31) != 0) return CODAG_E_INVALID_ARGUMENT;
     uint32_t in_len = (uint32_t)(i1 - i0), out_len = (uint32_t)(o1 - o0);
     uint8_t *dst = out + o0;
-    InRing in;
+    typename RingOf<Codec>::T in;
     int st;
     if constexpr (Codec == CODAG_DEFLATE) {
         if (in_len >= (1u << 28)) return CODAG_E_INVALID_ARGUMENT;  // bit counts fit 31 bits

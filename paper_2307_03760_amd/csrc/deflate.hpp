@@ -875,7 +875,7 @@ __device__ __forceinline__ int decode_deflate(Ring &in, uint8_t *out, uint32_t c
             uint32_t p = bi.byte_pos();
             if (p + len > in.gend) { st = CODAG_E_TRUNCATED; break; }
             for (uint32_t done = 0; done < len;) {
-                uint32_t piece = min(len - done, 512u);
+                uint32_t piece = min(len - done, Ring::kFetch / 2);
                 o.make_room(piece);
                 in.ensure(p + done + piece + 4);
                 uint32_t dst = o.o0 + o.pos;

@@ -90,7 +90,7 @@ __device__ __forceinline__ int lz4_sequence(Ring &in, WindowOut<H> &o, uint32_t 
         o.room -= lit;
     } else {
         for (uint32_t k = 0; k < lit;) {
-            const uint32_t piece = min(lit - k, 512u);
+            const uint32_t piece = min(lit - k, Ring::kFetch / 2);
             o.make_room(piece);
             in.ensure(q + k + piece + 4);
             const uint32_t dst = o.o0 + o.pos;

@@ -148,6 +148,89 @@ struct InRingT {
 };
 using InRing = InRingT<kFetchBytes>;
 
+// An input ring without a landing buffer or fetch-ahead: each fetch of F
+// bytes (F = 512, or a multiple of 1 KiB) lands straight in the ring half
+// whose bytes are no longer needed, and the wave waits for it.  For decoders
+// that spend tens of microseconds on a kilobyte of input (Deflate, LZ4) the
+// wait costs a few percent, and the LDS it saves (a landing buffer and, at
+// F = 512, half the ring) is what limits how many of their waves a CU holds.
+// Same interface and guarantee as InRingT: after ensure(end), bytes
+// [end - F, end) are readable; bytes past the chunk read as zero.
+template <uint32_t F>
+struct DirectRing {
+    static_assert(F == 512 || F % 1024 == 0, "fetch size");
+    static constexpr uint32_t kFetch = F, kBytes = 2 * F, kWords = kBytes / 4;
+    static constexpr uint32_t kLdsWords = kWords + 4, kLand = 0;
+    static constexpr uint32_t kLanes = F < 1024 ? F / 16 : kWave;  // lanes per fetch instruction
+    static constexpr uint32_t kIssues = (F + 1023) / 1024;
+
+    const uint8_t *gbase;  // 16-byte aligned
+    uint32_t skip;         // chunk start relative to gbase (0..15)
+    uint32_t gend;         // one past the chunk's last byte, relative to gbase
+    uint32_t loaded;       // bytes [loaded - F, loaded) are in the ring (and
+                           // [loaded - 2F, loaded - F) after two fetches in a row)
+    uint32_t *ring;        // this wave's ring (kLdsWords words)
+
+    __device__ __forceinline__ void init(const uint8_t *chunk, uint32_t len, uint32_t *ring_lds, uint32_t *) {
+        skip = (uint32_t)(reinterpret_cast<uintptr_t>(chunk) & 15);
+        gbase = chunk - skip;
+        gend = skip + len;
+        loaded = 0;
+        ring = ring_lds;
+    }
+
+    // Fetch [loaded, loaded + F) into the half that held [loaded - 2F,
+    // loaded - F): every caller needs only bytes at or past loaded + 1 - F
+    // from here on.  The half's earlier LDS reads have returned (their values
+    // were consumed), so the fetch cannot overtake them.
+    __device__ __forceinline__ void commit() {
+        const uint32_t half = (loaded / F) & 1;
+        uint32_t *dst = ring + half * (F / 4);
+#pragma unroll
+        for (uint32_t k = 0; k < kIssues; k++) {
+            const uint32_t at = loaded + 1024 * k + 16 * lane();
+            if (lane() < kLanes && at < gend)
+                __builtin_amdgcn_global_load_lds(gbase + at, (lds_void *)(dst + 256 * k), 16, 0, 0);
+        }
+        wait_vm();
+        if (loaded + F > gend) {  // zero the bytes past the end of the chunk
+#pragma unroll
+            for (uint32_t k = 0; k < kIssues; k++) {
+                const uint32_t at = loaded + 1024 * k + 16 * lane();
+                if (lane() < kLanes && at + 16 > gend) {
+                    const uint32_t valid = at < gend ? gend - at : 0;
+                    uint4 v = valid ? reinterpret_cast<const uint4 *>(dst)[64 * k + lane()] : make_uint4(0, 0, 0, 0);
+                    uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        int keep = (int)valid - 4 * j;
+                        uint32_t m = keep >= 4 ? 0xffffffffu : keep <= 0 ? 0u : ((1u << (8 * keep)) - 1);
+                        w[j] &= m;
+                    }
+                    reinterpret_cast<uint4 *>(dst)[64 * k + lane()] = make_uint4(w[0], w[1], w[2], w[3]);
+                }
+            }
+        }
+        if (half == 0 && lane() == 0)  // mirror of the first 16 bytes past the ring's end
+            reinterpret_cast<uint4 *>(ring)[kBytes / 16] = reinterpret_cast<const uint4 *>(ring)[0];
+        loaded += F;
+    }
+
+    __device__ __forceinline__ void ensure(uint32_t end) {
+        while (loaded < end) commit();
+    }
+
+    __device__ __forceinline__ void restart(uint32_t pos) { loaded = pos & ~(F - 1); }
+
+    __device__ __forceinline__ uint32_t word(uint32_t w) const { return ring[w & (kWords - 1)]; }
+    __device__ __forceinline__ uint32_t word_next(uint32_t w) const {
+        return ring[(w & (kWords - 1)) + 1];
+    }
+    __device__ __forceinline__ uint32_t word_at(uint32_t w, uint32_t k) const {
+        return ring[(w & (kWords - 1)) + k];
+    }
+};
+
 // Sixteen bytes at position pos as little-endian (lo, hi) pairs, per lane
 // (needs the five words from pos >> 2 readable).
 template <class Ring>

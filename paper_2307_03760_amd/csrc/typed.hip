@@ -120,8 +120,8 @@ template <int Codec>
 __global__ void __launch_bounds__(kWave)
     orc_frame_decode(const uint8_t *framed, uint32_t block, uint8_t *out, uint64_t out_cap,
                      const OrcFrame *frames, OrcMeta *meta) {
-    __shared__ __align__(16) uint32_t s_ring[kRingLdsWords];
-    __shared__ __align__(16) uint32_t s_land[kLandWords];
+    __shared__ __align__(16) uint32_t s_ring[ring_lds_words<Codec>()];
+    __shared__ __align__(16) uint32_t s_land[land_lds_words<Codec>()];
     __shared__ __align__(16) WaveScratch<Codec, 9, 4096> s_lds;
     const uint32_t count = uni(meta->count), complete = uni(meta->complete);
     for (uint32_t f = blockIdx.x; f < count; f += gridDim.x) {
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(kWave)
         } else if (len >= (1u << 28)) {
             st = CODAG_E_INVALID_ARGUMENT;
         } else {
-            InRing in;
+            typename RingOf<Codec>::T in;
             in.init(framed + src, len, s_ring, s_land);
             if constexpr (Codec == CODAG_DEFLATE)
                 st = decode_deflate<9, 4096>(in, out + at, room, &s_lds.t, &made);

@@ -121,6 +121,49 @@ def test_lz4_long_fields(dev):
     assert (assert_parity(oracle.LZ4, ch, dev) == 0).all()
 
 
+def _literal_block(data: bytes) -> bytes:
+    """An LZ4 block of one literal-only sequence."""
+    n = len(data)
+    b = bytearray([min(n, 15) << 4])
+    if n >= 15:
+        v = n - 15
+        while v >= 255:
+            b.append(255)
+            v -= 255
+        b.append(v)
+    return bytes(b) + data
+
+
+def test_lz4_input_fetch_boundaries(dev):
+    """Blocks whose compressed length falls at and around multiples of the
+    decoder's 512-byte input fetch, at many start alignments, with literal
+    runs read in several pieces; and greedy blocks of nearby lengths."""
+    rng = np.random.default_rng(22)
+    blobs, sizes, boundary = [], [], []
+    for k in (1, 2, 3, 4, 8):
+        for d in (-17, -16, -5, -1, 0, 1, 5, 16, 17):
+            # A small block first, so that this one starts at the next of the
+            # 16 alignments in turn.
+            at = sum(len(b) for b in blobs)
+            pad = bytes((len(boundary) - at - 1) % 16)
+            blobs.append(_literal_block(pad))
+            sizes.append(len(pad))
+            boundary.append(len(blobs))
+            target = 512 * k + d
+            n = next(n for n in range(target, 0, -1) if len(_literal_block(bytes(n))) <= target)
+            data = rng.integers(0, 256, n, dtype=np.uint8).tobytes()
+            blobs.append(_literal_block(data))
+            sizes.append(n)
+    for i in range(24):
+        data = workloads.zipf_text(int(rng.integers(600, 9000)), rng, workloads._vocab(0))
+        blobs.append(lz4_greedy(data) if i % 2 else workloads.lz4_block(data))
+        sizes.append(len(data))
+    ch = _chunks(blobs, sizes)
+    assert len({int(ch.chunk_offsets[i]) % 16 for i in boundary}) == 16
+    _say(f"lz4 fetch boundaries chunks={ch.n_chunks}")
+    assert (assert_parity(oracle.LZ4, ch, dev) == 0).all()
+
+
 def test_lz4_unaligned_layout(dev):
     """Compressed chunks and output ranges at odd offsets."""
     rng = np.random.default_rng(8)

@@ -159,6 +159,47 @@ def test_unaligned_chunk_layout(dev):
     assert (assert_parity(oracle.DEFLATE, ch, dev) == 0).all()
 
 
+def _stored(payload: bytes, final: bool = True) -> bytes:
+    """One stored block (RFC 1951 section 3.2.4): header byte, LEN, NLEN, bytes."""
+    n = len(payload)
+    return bytes([int(final)]) + n.to_bytes(2, "little") + (n ^ 0xFFFF).to_bytes(2, "little") + payload
+
+
+def test_deflate_input_fetch_boundaries(dev):
+    """Compressed lengths at and around multiples of the decoder's 512-byte
+    input fetch (a single stored block is its payload plus 5 bytes), chunk
+    starts at many alignments, stored runs read in several pieces, and
+    Huffman streams of lengths spread over the residues: bytes past a
+    chunk's end must read as zero and each ring half must hold the bytes
+    the decoder asks for."""
+    rng = np.random.default_rng(21)
+    blobs, sizes, boundary = [], [], []
+    for k in (1, 2, 3, 4, 8):
+        for d in (-17, -16, -5, -1, 0, 1, 5, 16, 17):
+            # A small chunk first, so that this one starts at the next of the
+            # 16 alignments in turn.
+            at = sum(len(b) for b in blobs)
+            pad = bytes((len(boundary) - at - 5) % 16)
+            blobs.append(_stored(pad))
+            sizes.append(len(pad))
+            payload = rng.integers(0, 256, 512 * k + d - 5, dtype=np.uint8).tobytes()
+            boundary.append(len(blobs))
+            blobs.append(_stored(payload))
+            sizes.append(len(payload))
+    for a, b in ((500, 20), (1, 1030), (255, 257), (4000, 3)):  # two stored blocks back to back
+        p, q = (rng.integers(0, 256, n, dtype=np.uint8).tobytes() for n in (a, b))
+        blobs.append(_stored(p, final=False) + _stored(q))
+        sizes.append(a + b)
+    for i in range(24):
+        d = workloads.zipf_text(int(rng.integers(600, 9000)), rng, workloads._vocab(0))
+        blobs.append(workloads.deflate_raw(d, fixed=bool(i % 2)))
+        sizes.append(len(d))
+    ch = _chunks(oracle.DEFLATE, blobs, sizes)
+    assert len({int(ch.chunk_offsets[i]) % 16 for i in boundary}) == 16
+    _say(f"deflate fetch boundaries chunks={ch.n_chunks}")
+    assert (assert_parity(oracle.DEFLATE, ch, dev) == 0).all()
+
+
 # ---- edge cases -------------------------------------------------------------
 
 def test_empty_and_degenerate(dev):
