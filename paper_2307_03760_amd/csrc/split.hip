@@ -568,6 +568,47 @@ __device__ __forceinline__ int v2_index_short_repeats(Ring &in, uint32_t &pos, u
     }
 }
 
+// Bit width of a 5-bit width code, and the width PATCHED_BASE patches are
+// stored at (0 when none fits), as scalar selects.
+__device__ __forceinline__ uint32_t v2_width(uint32_t code) {
+    const uint32_t high = (uint32_t)(0x40383028201E1C1Aull >> (8 * ((code - 24) & 7))) & 0xff;
+    return code < 24 ? code + 1 : high;  // 26, 28, 30, 32, 40, 48, 56, 64
+}
+__device__ __forceinline__ uint32_t v2_fit_width(uint32_t n) {
+    const uint32_t w = n <= 32 ? (n + 1) & ~1u : (n + 7) & ~7u;
+    return n <= 24 ? n : n <= 64 ? w : 0u;
+}
+
+// Bytes and value count of the DIRECT, PATCHED_BASE or DELTA run whose
+// header starts x (bytes 0-7 of the run; y and z bytes 8-23), without
+// branches; ok false where the run needs the step-by-step checks (a
+// PATCHED_BASE patch width that fits nothing, a DELTA varint longer than 8
+// bytes).
+__device__ __forceinline__ uint32_t v2_long_run(uint64_t x, uint64_t y, uint64_t z, uint32_t &len, bool &ok) {
+    const uint32_t b0 = (uint32_t)x & 0xff, b1 = (uint32_t)(x >> 8) & 0xff;
+    const uint32_t b2 = (uint32_t)(x >> 16) & 0xff, b3 = (uint32_t)(x >> 24) & 0xff;
+    const uint32_t type = b0 >> 6, code = (b0 >> 1) & 31, w = v2_width(code);
+    len = (((b0 & 1) << 8) | b1) + 1;
+    const uint32_t data = (len * w + 7) >> 3;
+    // PATCHED_BASE: 4 header bytes, the base, the data, the patches.
+    const uint32_t ew = v2_fit_width(((b3 >> 5) + 1) + v2_width(b2 & 31));
+    const uint32_t adv_p = 4 + ((b2 >> 5) + 1) + data + (((b3 & 31) * ew + 7) >> 3);
+    // DELTA: two varints from byte 2, then len - 2 deltas of width w (none
+    // for width code 0).
+    const uint64_t u1 = (x >> 16) | (y << 48);
+    const uint64_t t1 = ~u1 & 0x8080808080808080ull;
+    const uint32_t s2 = 2 + (uint32_t)(__builtin_ctzll(t1 | (1ull << 63)) >> 3) + 1;  // 3..10
+    const uint32_t sh = 8 * (s2 & 7);
+    const uint64_t lo = s2 < 8 ? x : y, hi = s2 < 8 ? y : z;
+    const uint64_t u2 = sh ? (lo >> sh) | (hi << (64 - sh)) : lo;
+    const uint64_t t2 = ~u2 & 0x8080808080808080ull;
+    const uint32_t s3 = s2 + (uint32_t)(__builtin_ctzll(t2 | (1ull << 63)) >> 3) + 1;
+    const uint32_t nd = len >= 2 ? len - 2 : 0u;
+    const uint32_t adv_t = s3 + ((nd * (code ? w : 0u) + 7) >> 3);
+    ok = type == 1 || (type == 2 && ew != 0) || (type == 3 && t1 != 0 && t2 != 0);
+    return type == 1 ? 2 + data : type == 2 ? adv_p : adv_t;
+}
+
 // Index pass, one wave per chunk: the checks of the decoder's header parse,
 // in its order.
 __global__ void __launch_bounds__(kWave * kV2IndexWpb)
@@ -603,12 +644,31 @@ __global__ void __launch_bounds__(kWave * kV2IndexWpb)
             break;
         }
         in.ensure(pos + 24);
-        const uint64_t x = in.peek8(pos);
+        // The 24 bytes from pos: lane k aligns their word k, and six lane
+        // reads bring them out (one LDS round trip).
+        const uint32_t wa = pos >> 2;
+        const uint32_t al = __builtin_amdgcn_alignbit(in.word(wa + lane() + 1), in.word(wa + lane()), 8 * (pos & 3));
+        const uint64_t x = ((uint64_t)readlane(al, 1) << 32) | readlane(al, 0);
         const uint32_t b0 = (uint32_t)(x & 0xff), type = b0 >> 6;
         if (type == 0) {
             st = v2_index_short_repeats(in, pos, end, nv, cap, j, sp, errnv);
             if (st) break;
             continue;
+        }
+        {
+            // A run that passes every check and starts no range moves on
+            // here; anything else takes the checks below.
+            const uint64_t y = ((uint64_t)readlane(al, 3) << 32) | readlane(al, 2);
+            const uint64_t z = ((uint64_t)readlane(al, 5) << 32) | readlane(al, 4);
+            uint32_t len;
+            bool ok;
+            const uint32_t adv = v2_long_run(x, y, z, len, ok);
+            const bool cut = j < kV2Ranges && nv >= v2_threshold(cap, j);
+            if (ok && !cut && len <= cap - nv && adv <= end - pos) {
+                pos += adv;
+                nv += len;
+                continue;
+            }
         }
         v2_cut(j, cap, pos, nv, sp);
         errnv = nv;
