@@ -565,25 +565,34 @@ __device__ __forceinline__ void lane_token(uint32_t s0, uint32_t s1, uint32_t s2
     const uint32_t wc = ALIGNED ? (k ? s3 : s2) : k == 0 ? s2 : k == 1 ? s3 : s4;
     const uint64_t x = ((uint64_t)__builtin_amdgcn_alignbit(wc, wb, sh) << 32) |
                        __builtin_amdgcn_alignbit(wb, wa, sh);
-    const uint32_t e = lds->lit[(uint32_t)x & ((1u << TB) - 1)];
+    const uint32_t xl = (uint32_t)x;
+    const uint32_t e = lds->lit[xl & ((1u << TB) - 1)];
     const uint32_t kind = e >> 13, cl = e & 15, sym = (e >> 4) & 511;
-    info = kTokOther;
-    dist = 0;
-    if (kind == kLit) {
-        info = (1u << 16) | (cl << 8) | sym;
-    } else if (kind == kEob) {
-        info = kTokStop | (cl << 8);
-    } else if (kind == kBase && have_dist) {
-        const uint32_t kk = sym - 257, ex = length_extra(kk);
-        const uint32_t len = length_base(kk) + ((uint32_t)(x >> cl) & ((1u << ex) - 1));
-        const uint32_t p2 = cl + ex;
-        const uint32_t d = lds->dist[(uint32_t)(x >> p2) & ((1u << kDistBits) - 1)];
-        if ((d >> 13) == kBase) {
-            const uint32_t dcl = d & 15, ds = (d >> 4) & 31, dex = dist_extra(ds);
-            dist = dist_base(ds) + ((uint32_t)(x >> (p2 + dcl)) & ((1u << dex) - 1));
-            info = (len << 16) | kTokCopy | ((p2 + dcl + dex) << 8);
-        }
-    }
+    // Every lane also decodes a length/distance pair from its bits (the
+    // distance lookup reads the table whatever the entry was) and the kind
+    // picks the result: no branches, so no scalar mask bookkeeping.  The
+    // length code and its extra bits end by bit 20, the distance code's
+    // index by bit 28, its extra bits by bit 50.
+    // The choices are all-ones/zero masks rather than conditionals, which
+    // the compiler would turn back into branches.
+    const uint32_t kk = (sym - 257) & 31;  // length symbol 257 + kk
+    const uint32_t lsmall = 0u - (uint32_t)(kk < 8), l258 = 0u - (uint32_t)(kk == 28);
+    const uint32_t ex = ((kk >> 2) - 1) & ~(lsmall | l258);
+    const uint32_t lbig = ((4 + (kk & 3)) << (((kk >> 2) - 1) & 31)) + 3;
+    const uint32_t lbase = (((kk + 3) & lsmall) | (lbig & ~lsmall) | l258) & (258u | ~l258);
+    const uint32_t len = lbase + ((xl >> cl) & ((1u << ex) - 1));
+    const uint32_t p2 = cl + ex;
+    const uint32_t d = lds->dist[(xl >> p2) & ((1u << kDistBits) - 1)];
+    const uint32_t dcl = d & 15, ds = (d >> 4) & 31, q = p2 + dcl;  // distance symbol ds
+    const uint32_t dsmall = 0u - (uint32_t)(ds < 4);
+    const uint32_t dex = ((ds >> 1) - 1) & ~dsmall;
+    const uint32_t dbase = ((ds + 1) & dsmall) | ((((2 + (ds & 1)) << dex) + 1) & ~dsmall);
+    const uint32_t dv = dbase + ((uint32_t)(x >> q) & ((1u << dex) - 1));
+    const uint32_t m_lit = 0u - (uint32_t)(kind == kLit), m_eob = 0u - (uint32_t)(kind == kEob);
+    const uint32_t m_copy = 0u - (uint32_t)(kind == kBase && have_dist && (d >> 13) == kBase);
+    info = (((1u << 16) | (cl << 8) | sym) & m_lit) | ((kTokStop | (cl << 8)) & m_eob) |
+           (((len << 16) | kTokCopy | ((q + dex) << 8)) & m_copy) | (kTokOther & ~(m_lit | m_eob | m_copy));
+    dist = dv & m_copy;
 }
 
 // A copy's distance packed into its token word: distance - 1 (15 bits) in
