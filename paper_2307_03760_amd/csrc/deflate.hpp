@@ -694,6 +694,7 @@ __device__ __forceinline__ int inflate_batched(Ring &in, BitIn &bi, WindowOut<H>
         uint32_t bout = budget - kBudget0 - 12 * ntok;
         __builtin_amdgcn_wave_barrier();
         const uint32_t tok = l < ntok ? stage[l] : 0u;
+        uint8_t *const trash = reinterpret_cast<uint8_t *>(stage) + 4 * l;
         const uint32_t tdist = (tok & kTokCopy) ? token_dist(tok) : 0u;
         // Output bounds, lane-parallel: the first token whose distance
         // reaches before the chunk or whose output would pass the end ends
@@ -756,8 +757,13 @@ __device__ __forceinline__ int inflate_batched(Ring &in, BitIn &bi, WindowOut<H>
                             v = (gv & m) | (v & ~m);
                         }
 #pragma unroll
-                        for (uint32_t b = 0; b < 4; b++)
-                            if (4 * j + b < n) o.win[o.slot(dst + r + 4 * j + b)] = (uint8_t)(v >> (8 * b));
+                        for (uint32_t b = 0; b < 4; b++) {
+                            // Bytes past the copy go to this lane's slot of
+                            // the (already read) token staging words, so
+                            // the sixteen stores need no lane masks.
+                            uint8_t *to = 4 * j + b < n ? o.win + o.slot(dst + r + 4 * j + b) : trash;
+                            *to = (uint8_t)(v >> (8 * b));
+                        }
                     }
                 }
             }
