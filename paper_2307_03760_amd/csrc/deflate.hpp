@@ -726,43 +726,69 @@ __device__ __forceinline__ int inflate_batched(Ring &in, BitIn &bi, WindowOut<H>
             // Bytes below lds_from may be overwritten in the window by this
             // batch; they were flushed to HBM before it started.
             const int32_t lds_from = (int32_t)(start + bout) - (int32_t)H;
-            if (ballot(before && (int32_t)src < lds_from)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            for (uint32_t r = 0; ballot(before && r < len); r += 16) {
-                if (before && r < len) {
-                    // Sixteen source bytes as five aligned words (from the
-                    // window, and from HBM where they fall below lds_from),
-                    // all loads issued before any is used; then byte stores.
-                    // HBM words may take up to three bytes either side of the
-                    // copy's range: the same aligned word, so the same
-                    // allocation; those bytes are discarded.
-                    const uint32_t n = min(len - r, 16u), q0 = src + r;
-                    const uint32_t a0 = q0 & ~3u, sh = q0 & 3;
-                    uint32_t w[5], g[5];
+            const bool far = ballot(before && (int32_t)src < lds_from) != 0;
+            if (!far) {
+                // Every source byte is in the window: no global loads, so
+                // nothing waits for the flushes still in flight.
+                for (uint32_t r = 0; ballot(before && r < len); r += 16) {
+                    if (before && r < len) {
+                        const uint32_t n = min(len - r, 16u), q0 = src + r;
+                        const uint32_t a0 = q0 & ~3u, sh = q0 & 3;
+                        uint32_t w[5];
 #pragma unroll
-                    for (uint32_t j = 0; j < 5; j++)
-                        w[j] = *reinterpret_cast<const uint32_t *>(o.win + o.slot(a0 + 4 * j));
-                    const int32_t nglob = lds_from - (int32_t)q0;  // leading bytes taken from HBM
-                    if (nglob > 0) {
-                        const uint32_t *gp = reinterpret_cast<const uint32_t *>(o.base + a0);
+                        for (uint32_t j = 0; j < 5; j++)
+                            w[j] = *reinterpret_cast<const uint32_t *>(o.win + o.slot(a0 + 4 * j));
 #pragma unroll
-                        for (uint32_t j = 0; j < 5; j++) g[j] = gp[j];
+                        for (uint32_t j = 0; j < 4; j++) {
+                            const uint32_t v = __builtin_amdgcn_alignbyte(w[j + 1], w[j], sh);
+#pragma unroll
+                            for (uint32_t b = 0; b < 4; b++) {
+                                // Bytes past the copy go to this lane's slot
+                                // of the (already read) token staging words,
+                                // so the sixteen stores need no lane masks.
+                                uint8_t *to = 4 * j + b < n ? o.win + o.slot(dst + r + 4 * j + b) : trash;
+                                *to = (uint8_t)(v >> (8 * b));
+                            }
+                        }
                     }
+                }
+            } else {
+                // Some source bytes were flushed: read them from HBM.
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                for (uint32_t r = 0; ballot(before && r < len); r += 16) {
+                    if (before && r < len) {
+                        // Sixteen source bytes as five aligned words (from the
+                        // window, and from HBM where they fall below lds_from),
+                        // all loads issued before any is used; then byte stores.
+                        // HBM words may take up to three bytes either side of the
+                        // copy's range: the same aligned word, so the same
+                        // allocation; those bytes are discarded.
+                        const uint32_t n = min(len - r, 16u), q0 = src + r;
+                        const uint32_t a0 = q0 & ~3u, sh = q0 & 3;
+                        uint32_t w[5], g[5];
 #pragma unroll
-                    for (uint32_t j = 0; j < 4; j++) {
-                        uint32_t v = __builtin_amdgcn_alignbyte(w[j + 1], w[j], sh);
-                        if (nglob > 4 * (int32_t)j) {
-                            uint32_t gv = __builtin_amdgcn_alignbyte(g[j + 1], g[j], sh);
-                            int32_t kb = nglob - 4 * (int32_t)j;  // bytes of this word from HBM
-                            uint32_t m = kb >= 4 ? 0xffffffffu : (1u << (8 * kb)) - 1;
-                            v = (gv & m) | (v & ~m);
+                        for (uint32_t j = 0; j < 5; j++)
+                            w[j] = *reinterpret_cast<const uint32_t *>(o.win + o.slot(a0 + 4 * j));
+                        const int32_t nglob = lds_from - (int32_t)q0;  // leading bytes taken from HBM
+                        if (nglob > 0) {
+                            const uint32_t *gp = reinterpret_cast<const uint32_t *>(o.base + a0);
+#pragma unroll
+                            for (uint32_t j = 0; j < 5; j++) g[j] = gp[j];
                         }
 #pragma unroll
-                        for (uint32_t b = 0; b < 4; b++) {
-                            // Bytes past the copy go to this lane's slot of
-                            // the (already read) token staging words, so
-                            // the sixteen stores need no lane masks.
-                            uint8_t *to = 4 * j + b < n ? o.win + o.slot(dst + r + 4 * j + b) : trash;
-                            *to = (uint8_t)(v >> (8 * b));
+                        for (uint32_t j = 0; j < 4; j++) {
+                            uint32_t v = __builtin_amdgcn_alignbyte(w[j + 1], w[j], sh);
+                            if (nglob > 4 * (int32_t)j) {
+                                uint32_t gv = __builtin_amdgcn_alignbyte(g[j + 1], g[j], sh);
+                                int32_t kb = nglob - 4 * (int32_t)j;  // bytes of this word from HBM
+                                uint32_t m = kb >= 4 ? 0xffffffffu : (1u << (8 * kb)) - 1;
+                                v = (gv & m) | (v & ~m);
+                            }
+#pragma unroll
+                            for (uint32_t b = 0; b < 4; b++) {
+                                uint8_t *to = 4 * j + b < n ? o.win + o.slot(dst + r + 4 * j + b) : trash;
+                                *to = (uint8_t)(v >> (8 * b));
+                            }
                         }
                     }
                 }
