@@ -666,7 +666,8 @@ __device__ __forceinline__ int inflate_batched(Ring &in, BitIn &bi, WindowOut<H>
             uint32_t w = readlane(walk, T & 63);
             uint64_t mark = 0;
             while (!((w | T) & (kWalkStop | kWindowEnd | kBudgetFull))) {
-                mark |= 1ull << (T & 63);
+                // One scalar instruction sets the bit (bit T mod 64).
+                asm volatile("s_bitset1_b64 %0, %1" : "+s"(mark) : "s"(T));
                 T += w;
                 w = readlane(walk, T & 63);
             }
@@ -765,7 +766,7 @@ __device__ __forceinline__ int inflate_batched(Ring &in, BitIn &bi, WindowOut<H>
                         // allocation; those bytes are discarded.
                         const uint32_t n = min(len - r, 16u), q0 = src + r;
                         const uint32_t a0 = q0 & ~3u, sh = q0 & 3;
-                        uint32_t w[5], g[5];
+                        uint32_t w[5], g[5] = {0, 0, 0, 0, 0};
 #pragma unroll
                         for (uint32_t j = 0; j < 5; j++)
                             w[j] = *reinterpret_cast<const uint32_t *>(o.win + o.slot(a0 + 4 * j));
@@ -775,15 +776,16 @@ __device__ __forceinline__ int inflate_batched(Ring &in, BitIn &bi, WindowOut<H>
 #pragma unroll
                             for (uint32_t j = 0; j < 5; j++) g[j] = gp[j];
                         }
+                        // Every loaded word is used here (masked), so no load
+                        // is left in flight past this loop: the wait for it
+                        // would also wait for every flush store.
 #pragma unroll
                         for (uint32_t j = 0; j < 4; j++) {
                             uint32_t v = __builtin_amdgcn_alignbyte(w[j + 1], w[j], sh);
-                            if (nglob > 4 * (int32_t)j) {
-                                uint32_t gv = __builtin_amdgcn_alignbyte(g[j + 1], g[j], sh);
-                                int32_t kb = nglob - 4 * (int32_t)j;  // bytes of this word from HBM
-                                uint32_t m = kb >= 4 ? 0xffffffffu : (1u << (8 * kb)) - 1;
-                                v = (gv & m) | (v & ~m);
-                            }
+                            const uint32_t gv = __builtin_amdgcn_alignbyte(g[j + 1], g[j], sh);
+                            const int32_t kb = nglob - 4 * (int32_t)j;  // bytes of this word from HBM
+                            const uint32_t m = kb >= 4 ? 0xffffffffu : kb <= 0 ? 0u : (1u << (8 * kb)) - 1;
+                            v = (gv & m) | (v & ~m);
 #pragma unroll
                             for (uint32_t b = 0; b < 4; b++) {
                                 uint8_t *to = 4 * j + b < n ? o.win + o.slot(dst + r + 4 * j + b) : trash;
