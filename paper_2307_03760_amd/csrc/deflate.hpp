@@ -626,7 +626,8 @@ __device__ __forceinline__ int inflate_batched(Ring &in, BitIn &bi, WindowOut<H>
     // token words, in the code-length scratch (free while symbols decode),
     // one word per token of the batch.
     uint32_t *stage = reinterpret_cast<uint32_t *>(lds->lens);
-    static_assert(sizeof(lds->lens) >= 4 * kWave, "staging space");
+    constexpr uint32_t kStageSpare = 64;  // 16 words no batch uses (at most 60 tokens)
+    static_assert(sizeof(lds->lens) >= 4 * (kStageSpare + 16), "staging space");
     uint32_t p = 8 * bi.next - bi.cnt;  // bit position of the next code
     // Input words [cend - 64, cend), one per lane, read from the ring once
     // per 240 bytes or so; a window takes its four words out with readlane.
@@ -641,23 +642,23 @@ __device__ __forceinline__ int inflate_batched(Ring &in, BitIn &bi, WindowOut<H>
         uint32_t stop = 0;  // 1 full, 2 end of block, 3 one symbol the slow way
         const uint32_t total0 = o.pos, p0 = p;
         uint32_t budget = kBudget0;
-        do {
-            if (!have) {
-                const uint32_t wi = 2 * wk;
-                if (wi + 4 > cend || wi + 64 < cend) {
-                    in.ensure(4 * (wi + 64) + 4);
-                    cache = in.word(wi + l);
-                    cend = wi + 64;
-                }
-                const uint32_t c0 = wi + 64 - cend;
-                uint32_t info, dist;
-                lane_token<TB, H, true>(readlane(cache, c0), readlane(cache, c0 + 1),
-                                        readlane(cache, c0 + 2), readlane(cache, c0 + 3), 0u, 64 * wk,
-                                        lds, have_dist, info, dist);
-                cur = pack_token(info, dist);
-                walk = walk_word(info);
-                have = true;
+        // Candidates of window wk: every lane's packed token and walk word.
+        auto candidates = [&]() {
+            const uint32_t wi = 2 * wk;
+            if (wi + 4 > cend || wi + 64 < cend) {
+                in.ensure(4 * (wi + 64) + 4);
+                cache = in.word(wi + l);
+                cend = wi + 64;
             }
+            const uint32_t c0 = wi + 64 - cend;
+            uint32_t info, dist;
+            lane_token<TB, H, true>(readlane(cache, c0), readlane(cache, c0 + 1), readlane(cache, c0 + 2),
+                                    readlane(cache, c0 + 3), 0u, 64 * wk, lds, have_dist, info, dist);
+            cur = pack_token(info, dist);
+            walk = walk_word(info);
+        };
+        if (!have) candidates();
+        for (;;) {
             // The walk follows token starts only, one lane read and one add
             // per token, until a token the batch cannot take, the end of the
             // window or a full batch (output bounds are checked lane-parallel
@@ -671,27 +672,33 @@ __device__ __forceinline__ int inflate_batched(Ring &in, BitIn &bi, WindowOut<H>
                 T += w;
                 w = readlane(walk, T & 63);
             }
-            // Stage this window's tokens in walk order.
-            if ((mark >> l) & 1) stage[ntok + count_below(mark)] = cur;
+            // Stage this window's tokens in walk order.  Lanes without one
+            // write a spare staging word past the batch's 60, so the store
+            // needs no lane mask.
+            const bool staged = (mark >> l) & 1;
+            stage[staged ? ntok + count_below(mark) : kStageSpare + (l & 15)] = cur;
             ntok += (uint32_t)__builtin_popcountll(mark);
             budget = T >> 8;
             const uint32_t t = T & 255;
             p = 64 * wk + t;
-            if (t >= 64) {  // into the next window (a token ends at most 48 bits past this one)
-                wk++;
-                have = false;
-            } else if (budget >= 1024) {
-                stop = 1;  // batch full
-            } else {
-                const uint32_t inf = readlane(cur, t);
-                if (inf == (kTokStop | (inf & 0x3f00))) {  // end of block
-                    p += (inf >> 8) & 63;
-                    stop = 2;
+            if (t < 64) {  // the batch ends in this window; its candidates stay
+                if (budget >= 1024) {
+                    stop = 1;  // batch full
                 } else {
-                    stop = 3;
+                    const uint32_t inf = readlane(cur, t);
+                    if (inf == (kTokStop | (inf & 0x3f00))) {  // end of block
+                        p += (inf >> 8) & 63;
+                        stop = 2;
+                    } else {
+                        stop = 3;
+                    }
                 }
+                have = true;
+                break;
             }
-        } while (stop == 0);
+            wk++;  // into the next window (a token ends at most 48 bits past this one)
+            candidates();
+        }
         uint32_t bout = budget - kBudget0 - 12 * ntok;
         __builtin_amdgcn_wave_barrier();
         const uint32_t tok = l < ntok ? stage[l] : 0u;
