@@ -701,15 +701,20 @@ __device__ __forceinline__ int inflate_batched(Ring &in, BitIn &bi, WindowOut<H>
         }
         uint32_t bout = budget - kBudget0 - 12 * ntok;
         __builtin_amdgcn_wave_barrier();
-        const uint32_t tok = l < ntok ? stage[l] : 0u;
+        // Every lane reads a staging word (all in bounds); lanes past the
+        // batch drop it.
+        const uint32_t staged = stage[l];
+        const uint32_t tok = l < ntok ? staged : 0u;
         uint8_t *const trash = reinterpret_cast<uint8_t *>(stage) + 4 * l;
         const uint32_t tdist = (tok & kTokCopy) ? token_dist(tok) : 0u;
+        // Each token's output length and offset in the chunk (one prefix sum
+        // for the bounds and the writes).
+        const uint32_t vlen = token_len(tok);
+        const uint32_t before = total0 + wave_inclusive_sum32(vlen) - vlen;
         // Output bounds, lane-parallel: the first token whose distance
         // reaches before the chunk or whose output would pass the end ends
         // the batch, and goes through the symbol-at-a-time path.
         if (ntok) {
-            const uint32_t vlen = l < ntok ? token_len(tok) : 0;
-            const uint32_t before = total0 + wave_inclusive_sum32(vlen) - vlen;
             const uint64_t badm = ballot(l < ntok && (tdist > before || before + vlen > o.cap));
             if (badm) {
                 const uint32_t j = (uint32_t)__builtin_ctzll(badm);
@@ -724,11 +729,12 @@ __device__ __forceinline__ int inflate_batched(Ring &in, BitIn &bi, WindowOut<H>
         // ---- write the batch
         if (ntok) {
             const bool valid = l < ntok;
-            const uint32_t len = valid ? token_len(tok) : 0;
+            const uint32_t len = valid ? vlen : 0;
             const bool is_copy = valid && (tok & kTokCopy);
             const uint32_t start = o.o0 + total0;  // first byte of the batch (window coordinates)
-            const uint32_t dst = start + wave_inclusive_sum32(len) - len;
-            if (valid && !is_copy) o.win[o.slot(dst)] = (uint8_t)tok;
+            const uint32_t dst = o.o0 + before;    // this token's first byte
+            uint8_t *const lit_to = valid && !is_copy ? o.win + o.slot(dst) : trash;
+            *lit_to = (uint8_t)tok;
             const uint32_t src = dst - tdist;
             const bool before = is_copy && src + len <= start;  // source entirely before the batch
             // Bytes below lds_from may be overwritten in the window by this
@@ -832,8 +838,10 @@ __device__ __forceinline__ int inflate_batched(Ring &in, BitIn &bi, WindowOut<H>
         int st = inflate_symbols<TB, H, true>(in, bi, o, lds, have_dist, len_tab, dist_tab);
         if (st != kMore) return st;
         p = 8 * bi.next - bi.cnt;
+        // A window's candidates depend only on its input bits: if the next
+        // token is still in window wk, they stay.
+        have = have && (p >> 6) == wk;
         wk = p >> 6;
-        have = 0;
     }
 }
 
