@@ -228,19 +228,22 @@ __global__ void __launch_bounds__(kIdxThreads)
                                                  : sb1 + __builtin_popcount(tb1 & ((1u << rb) - 1));
                     const uint32_t cntl = 256 - hb;
                     const uint32_t ti = tcnt + (run ? 0u : cntl - 1);
-                    const uint32_t e = ti < total ? s_tpos[ti] : kIdxRegion;
-                    if (run) {
-                        const uint32_t nb = e - r + 1;
-                        uint32_t code = kEntOk;
-                        if (W + r > end) code = kEntTruncated;
-                        else if (nb > 10 || (nb == 10 && ((buf[e >> 2] >> (8 * (e & 3))) & 0xff) > 1))
-                            code = kEntCorrupt;
-                        else if (W + e >= end) code = kEntTruncated;
-                        e4[i] = make_ent(code == kEntOk ? e + 1 - p : 0, hb + 3, code);
-                    } else {
-                        const bool open = e >= kIdxRegion || W + e >= end;
-                        e4[i] = make_ent(open ? 0 : e + 1 - p, cntl, open ? kEntOpen : kEntOk);
-                    }
+                    // Every lane looks up (index clamped into the table) and
+                    // builds both kinds of entry; selects pick one, so there
+                    // are no lane-masked branches.
+                    const uint32_t tp = s_tpos[min(ti, kIdxRegion - 1)];
+                    const uint32_t e = ti < total ? tp : kIdxRegion;
+                    const uint32_t nb = e - r + 1;
+                    uint32_t eb = 0;  // a 10-byte varint's last byte (rare: read only when some lane needs it)
+                    if (ballot(run && nb == 10)) eb = (buf[min(e >> 2, kIdxWords - 1)] >> (8 * (e & 3))) & 0xff;
+                    const uint32_t rcode = W + r > end                        ? kEntTruncated
+                                           : nb > 10 || (nb == 10 && eb > 1) ? kEntCorrupt
+                                           : W + e >= end                    ? kEntTruncated
+                                                                              : kEntOk;
+                    const uint32_t ent_run = make_ent(rcode == kEntOk ? e + 1 - p : 0, hb + 3, rcode);
+                    const bool open = e >= kIdxRegion || W + e >= end;
+                    const uint32_t ent_lit = make_ent(open ? 0 : e + 1 - p, cntl, open ? kEntOpen : kEntOk);
+                    e4[i] = run ? ent_run : ent_lit;
                 }
                 reinterpret_cast<uint4 *>(ent)[q] = make_uint4(e4[0], e4[1], e4[2], e4[3]);
             }
