@@ -120,6 +120,61 @@ def test_batch_given_orders(dev, small, kind):
     compare_chunks(*res, ref, ref_st, ch.out_offsets)
 
 
+def _interleaved_layout(ch):
+    """The same chunks re-indexed so that the codecs alternate in the chunk
+    array itself (round robin over RLE v1, RLE v2, Deflate), with a pad chunk
+    (empty input, 1-7 output bytes, so it fails as TRUNCATED before writing)
+    wherever an RLE chunk's output would otherwise start unaligned.  Returns
+    the layout and, per chunk of it, the original chunk index (-1 for pads)."""
+    codecs = np.asarray(ch.codecs)
+    by_codec = [list(np.nonzero(codecs == c)[0]) for c in (oracle.RLE_V1, oracle.RLE_V2, oracle.DEFLATE)]
+    seq = []
+    while any(by_codec):
+        for q in by_codec:
+            if q:
+                seq.append(int(q.pop(0)))
+    out_codecs, blobs, sizes, src = [], [], [], []
+    at = 0
+    for i in seq:
+        c = int(codecs[i])
+        if c != oracle.DEFLATE and at % 8:
+            out_codecs.append(oracle.DEFLATE)
+            blobs.append(np.zeros(0, np.uint8))
+            sizes.append(8 - at % 8)
+            src.append(-1)
+            at += 8 - at % 8
+        a, b = int(ch.chunk_offsets[i]), int(ch.chunk_offsets[i + 1])
+        n_out = int(ch.out_offsets[i + 1] - ch.out_offsets[i])
+        out_codecs.append(c)
+        blobs.append(np.asarray(ch.comp[a:b]))
+        sizes.append(n_out)
+        src.append(i)
+        at += n_out
+    return workloads._pack(out_codecs, blobs, sizes), np.array(src)
+
+
+@pytest.mark.parametrize("order", ["index", "codec"])
+def test_batch_codec_interleaved_layout(dev, small, order):
+    """Chunks whose codecs alternate in the chunk array (not only in the queue
+    order) decode bit-exactly, pads between them stay unwritten, and the
+    codec-grouped queue order gives the same result on that layout."""
+    import paper_2307_03760_amd as codag
+    ch, _, _ = small
+    lay, src = _interleaved_layout(ch)
+    assert (np.diff(lay.codecs.astype(np.int64)) != 0).mean() > 0.5
+    ref, ref_st = oracle_mixed(lay.codecs, lay.comp, lay.chunk_offsets, lay.out_offsets)
+    assert (ref_st[src >= 0] == 0).all() and (ref_st[src < 0] == oracle.E_TRUNCATED).all()
+    _say(f"batch interleaved layout order={order} chunks={lay.n_chunks}")
+    plan = codag.Plan(order=codag.ORDER_CODEC if order == "codec" else codag.ORDER_INDEX)
+    (res,), _ = _run(plan, lay, dev)
+    got, got_st = res
+    compare_chunks(got, got_st, ref, ref_st, lay.out_offsets)
+    for k in np.nonzero(src < 0)[0]:
+        a, b = int(lay.out_offsets[k]), int(lay.out_offsets[k + 1])
+        assert (got[a:b] == GUARD_BYTE).all(), f"pad chunk {k} written"
+    plan.close()
+
+
 def test_batch_graph_replays(dev, small):
     """A captured graph replayed three times, with eager work between the
     replays (clearing the output and status), gives the full result each time."""
