@@ -35,6 +35,13 @@
  *   - Huffman codes are peeked with zero bits past the end of input; a
  *     bit pattern matching no code is CORRUPT, a matching code that runs
  *     past the end is TRUNCATED.
+ *   - A PATCHED_BASE patch entry after the first with a zero gap ORs its
+ *     patch into the value the entry before it patched.
+ *
+ * Which status a rejected stream gets (TRUNCATED, CORRUPT, OVERFLOW, ...)
+ * beyond the hand-worked cases is parity unpinned: no independent decoder
+ * reports these statuses.  Whether an RLE stream is accepted, and what it
+ * decodes to, is pinned one-sidedly against Apache ORC's reader.
  */
 #include "oracle.h"
 
