@@ -313,6 +313,35 @@ def test_corrupt_streams_status_parity(dev, codec, gp):
     assert (st != 0).sum() > 100
 
 
+
+@pytest.mark.parametrize("version,gp", [("0.11", 1), ("0.11", 2), ("0.12", 1), ("0.12", 2)])
+def test_orc_writer_streams_damaged(dev, tmp_path, version, gp):
+    """Integer DATA streams written by Apache ORC's writer (through pyarrow),
+    as written and damaged in one to three bytes: GPU output and statuses
+    equal the oracle's on both RLE paths."""
+    pa = pytest.importorskip("pyarrow")
+    po = pytest.importorskip("pyarrow.orc")
+    from orc_walk import integer_data_streams
+    from test_oracle_rle_mutants import _values
+    rng = np.random.default_rng([77, gp, 0 if version == "0.11" else 1])
+    values = _values(rng)
+    path = str(tmp_path / "t.orc")
+    po.write_table(pa.table({"x": pa.array(values, type=pa.int64())}), path,
+                   file_version=version, compression="uncompressed")
+    kind, streams = integer_data_streams(path)
+    codec = oracle.RLE_V1 if kind == 0 else oracle.RLE_V2
+    s = streams[0]
+    muts = [s]
+    for _ in range(300):
+        b = bytearray(s)
+        for _ in range(int(rng.integers(1, 4))):
+            b[int(rng.integers(0, len(b)))] = int(rng.integers(0, 256))
+        muts.append(bytes(b))
+    ch = _chunks(codec, muts, [8 * values.size] * len(muts))
+    _say(f"orc-written damaged codec={codec} group_parallel={gp} chunks={ch.n_chunks}")
+    st = assert_parity(codec, ch, dev, group_parallel=gp)
+    assert st[0] == 0 and (st != 0).any()
+
 # ---- full workload sizes, benchmark launch configuration ---------------------
 
 @pytest.mark.parametrize("gp", [0, 1])
