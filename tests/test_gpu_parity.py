@@ -342,6 +342,32 @@ def test_orc_writer_streams_damaged(dev, tmp_path, version, gp):
     st = assert_parity(codec, ch, dev, group_parallel=gp)
     assert st[0] == 0 and (st != 0).any()
 
+
+def test_orc_writer_byte_rle_damaged(dev, tmp_path):
+    """The byte RLE DATA stream of a byte column written by Apache ORC's
+    writer, as written and damaged in one to three bytes: GPU output and
+    statuses equal the oracle's."""
+    pa = pytest.importorskip("pyarrow")
+    po = pytest.importorskip("pyarrow.orc")
+    from orc_walk import integer_data_streams
+    rng = np.random.default_rng([78, 4])
+    values = np.concatenate([np.repeat(rng.integers(-128, 128, 60), rng.integers(1, 40, 60)),
+                             rng.integers(-128, 128, 2000)]).astype(np.int8)
+    path = str(tmp_path / "b.orc")
+    po.write_table(pa.table({"x": pa.array(values, type=pa.int8())}), path, compression="uncompressed")
+    _, streams = integer_data_streams(path)
+    s = streams[0]
+    muts = [s]
+    for _ in range(300):
+        b = bytearray(s)
+        for _ in range(int(rng.integers(1, 4))):
+            b[int(rng.integers(0, len(b)))] = int(rng.integers(0, 256))
+        muts.append(bytes(b))
+    ch = _chunks(oracle.BYTE_RLE, muts, [values.size] * len(muts))
+    _say(f"orc-written damaged byte RLE chunks={ch.n_chunks}")
+    st = assert_parity(oracle.BYTE_RLE, ch, dev)
+    assert st[0] == 0 and (st != 0).any()
+
 # ---- full workload sizes, benchmark launch configuration ---------------------
 
 @pytest.mark.parametrize("gp", [0, 1])

@@ -135,3 +135,48 @@ def test_mutated_streams_against_orc_reader(tmp_path, version):
             counts["oracle_stricter"] += 1
     assert counts["same"] > 0 and counts["both_reject"] > 0
     assert counts["pb_zero_gap"] <= 10, counts
+
+
+def test_mutated_byte_rle_against_orc_reader(tmp_path):
+    """The same one-sided pin for ORC byte RLE (the DATA stream of a byte
+    column): runs of repeated bytes and literal stretches."""
+    rng = np.random.default_rng([2024, 2])
+    values = np.concatenate([np.repeat(rng.integers(-128, 128, 60), rng.integers(1, 40, 60)),
+                             rng.integers(-128, 128, 2000)]).astype(np.int8)
+    n = values.size
+    path = str(tmp_path / "b.orc")
+    po.write_table(pa.table({"x": pa.array(values, type=pa.int8())}), path, compression="uncompressed")
+    _, streams = integer_data_streams(path)
+    assert len(streams) == 1
+    data = open(path, "rb").read()
+    s = streams[0]
+    assert data.count(s) == 1
+    off = data.find(s)
+    st, out = oracle.decode_chunk(oracle.BYTE_RLE, s, n)
+    assert st == oracle.OK and np.array_equal(np.frombuffer(out, np.int8), values)
+
+    counts = {"same": 0, "both_reject": 0, "oracle_stricter": 0}
+    mpath = str(tmp_path / "m.orc")
+    for _ in range(250):
+        m = bytearray(data)
+        for _ in range(int(rng.integers(1, 4))):
+            m[off + int(rng.integers(0, len(s)))] = int(rng.integers(0, 256))
+        with open(mpath, "wb") as f:
+            f.write(m)
+        st, out = oracle.decode_chunk(oracle.BYTE_RLE, bytes(m[off:off + len(s)]), n)
+        ov = np.frombuffer(out, np.int8)
+        try:
+            got = po.read_table(mpath).column(0).to_numpy()
+        except Exception:  # Apache ORC rejected the stream
+            assert st != oracle.OK, "the oracle accepts a stream Apache ORC rejects"
+            counts["both_reject"] += 1
+            continue
+        assert got.size == n
+        if st == oracle.OK:
+            np.testing.assert_array_equal(ov, got)
+            counts["same"] += 1
+        else:
+            assert st in (oracle.E_OVERFLOW, oracle.E_CORRUPT), st
+            np.testing.assert_array_equal(ov, got[:ov.size])
+            counts["oracle_stricter"] += 1
+    assert counts["same"] > 0 and counts["both_reject"] > 0
