@@ -225,3 +225,43 @@ def test_orc_file_end_to_end(dev, tmp_path, version, block, compression):
                                   np.unpackbits(np.frombuffer(expect, np.uint8))[:n])
         else:
             assert got == expect, (col, kind)
+
+
+def test_orc_zlib_stream_damaged(dev, tmp_path):
+    """The framed DATA stream of a ZLIB-compressed file written by Apache
+    ORC's writer, as written and damaged in one to three bytes: the GPU's
+    framing and Deflate decode gives the oracle's status and bytes, and the
+    streams that inflate decode on the GPU like the oracle's RLE v2."""
+    pa = pytest.importorskip("pyarrow")
+    po = pytest.importorskip("pyarrow.orc")
+    from orc_walk import DATA, file_streams
+    from test_oracle_rle_mutants import _values
+    rng = np.random.default_rng([79, 1])
+    values = _values(rng)
+    path = str(tmp_path / "z.orc")
+    po.write_table(pa.table({"x": pa.array(values, type=pa.int64())}), path, file_version="0.12",
+                   compression="zlib", compression_block_size=65536)
+    f = file_streams(path)
+    raw, block = f["stripes"][0]["streams"][(1, DATA)], f["block_size"]
+    cap = 1 << 20
+    inflated = []
+    n_bad = 0
+    for k in range(121):
+        b = bytearray(raw)
+        if k:
+            for _ in range(int(rng.integers(1, 4))):
+                b[int(rng.integers(0, len(b)))] = int(rng.integers(0, 256))
+        ref_st, ref = oracle.orc_inflate_stream(bytes(b), block, cap)
+        got_st, got = _gpu_inflate(bytes(b), block, cap, dev)
+        assert got_st == ref_st, (k, got_st, ref_st)
+        if ref_st == oracle.OK:
+            assert got == ref, k
+            inflated.append(ref)
+        else:
+            n_bad += 1
+    assert n_bad > 0 and len(inflated) > 10
+    _say(f"orc zlib damaged: {n_bad} streams rejected by the framing or Deflate, {len(inflated)} decoded")
+    ch = workloads._pack([oracle.RLE_V2] * len(inflated), inflated, [8 * values.size] * len(inflated))
+    for gp in (1, 2):
+        st = assert_parity(oracle.RLE_V2, ch, dev, group_parallel=gp)
+        assert st[0] == 0

@@ -1,6 +1,8 @@
-"""The oracle's RLE v1 / RLE v2 acceptance rules pinned against an independent
-reader: Apache ORC's own (through pyarrow), on integer DATA streams that
-pyarrow wrote and that the test then damages in one to three bytes.
+"""The oracle's RLE v1 / RLE v2 / byte RLE acceptance rules pinned against an
+independent reader: Apache ORC's own (through pyarrow), on DATA streams that
+pyarrow wrote and that the test then damages in one to three bytes (for a
+ZLIB-compressed file, in the framed bytes, so the oracle's framing and
+Deflate decoder are pinned along).
 
 Apache ORC's reader decodes exactly the column's value count and reports
 no status codes, so the pin is one-sided:
@@ -180,3 +182,65 @@ def test_mutated_byte_rle_against_orc_reader(tmp_path):
             np.testing.assert_array_equal(ov, got[:ov.size])
             counts["oracle_stricter"] += 1
     assert counts["same"] > 0 and counts["both_reject"] > 0
+
+
+def test_mutated_zlib_streams_against_orc_reader(tmp_path):
+    """The same one-sided pin through ORC's compression framing: an RLE v2
+    DATA stream of a ZLIB-compressed file, damaged in its framed bytes
+    (chunk headers and raw Deflate), read by the oracle's framing and
+    Deflate decoder and then its RLE v2 decoder.  A stream Apache ORC reads
+    is one the oracle's framing and Deflate accept."""
+    from orc_walk import DATA, file_streams
+    rng = np.random.default_rng([2024, 3])
+    values = _values(rng)
+    n = values.size
+    path = str(tmp_path / "z.orc")
+    po.write_table(pa.table({"x": pa.array(values, type=pa.int64())}), path, file_version="0.12",
+                   compression="zlib", compression_block_size=65536)
+    f = file_streams(path)
+    assert f["compression"] == 1 and len(f["stripes"]) == 1
+    raw, block = f["stripes"][0]["streams"][(1, DATA)], f["block_size"]
+    data = open(path, "rb").read()
+    assert data.count(raw) == 1
+    off = data.find(raw)
+    big = 1 << 22
+
+    def oracle_read(framed):
+        st, dec = oracle.orc_inflate_stream(framed, block, big)
+        if st != oracle.OK:
+            return st, None, None
+        st, out = oracle.decode_chunk(oracle.RLE_V2, bytes(dec), 8 * n)
+        return st, np.frombuffer(out, np.int64), bytes(dec)
+
+    st, ov, _ = oracle_read(raw)
+    assert st == oracle.OK and np.array_equal(ov, values)
+
+    counts = {"same": 0, "both_reject": 0, "oracle_stricter": 0, "pb_zero_gap": 0}
+    mpath = str(tmp_path / "m.orc")
+    for _ in range(250):
+        m = bytearray(data)
+        for _ in range(int(rng.integers(1, 4))):
+            m[off + int(rng.integers(0, len(raw)))] = int(rng.integers(0, 256))
+        with open(mpath, "wb") as fh:
+            fh.write(m)
+        st, ov, dec = oracle_read(bytes(m[off:off + len(raw)]))
+        try:
+            got = po.read_table(mpath).column(0).to_numpy()
+        except Exception:  # Apache ORC rejected the stream
+            assert st != oracle.OK, "the oracle accepts a stream Apache ORC rejects"
+            counts["both_reject"] += 1
+            continue
+        assert dec is not None, "Apache ORC reads a stream whose framing or Deflate the oracle rejects"
+        if _pb_zero_gap(dec):
+            counts["pb_zero_gap"] += 1
+            continue
+        assert got.size == n
+        if st == oracle.OK:
+            np.testing.assert_array_equal(ov, got)
+            counts["same"] += 1
+        else:
+            assert st in (oracle.E_OVERFLOW, oracle.E_CORRUPT), st
+            np.testing.assert_array_equal(ov, got[:ov.size])
+            counts["oracle_stricter"] += 1
+    assert counts["same"] > 0 and counts["both_reject"] > 0
+    assert counts["pb_zero_gap"] < 125, counts
