@@ -168,3 +168,42 @@ def test_orc_lz4_file_streams(tmp_path, block_size):
     assert chars == "".join(words).encode()
     st, lens = oracle.orc_inflate_stream(sf["streams"][(2, LENGTH)], block_size, 1 << 24, codec=oracle.LZ4)
     assert st == oracle.OK and len(lens) > 0
+
+
+@pytest.mark.parametrize("kind", ["text", "int32", "runs"])
+def test_damaged_blocks_against_reference_library(kind):
+    """Blocks written by pyarrow's LZ4 and damaged in one to three bytes,
+    decoded by the oracle and by the reference library (pyarrow's
+    "lz4_raw" decompress, told the original size).  That library reports no
+    status codes and, as pyarrow calls it, does not check that a block fills
+    the size it was told, so the pin is one-sided: a block the oracle
+    accepts gives the same bytes in both; a block the library rejects, the
+    oracle rejects; a block only the oracle rejects is UNDERFLOW (it ends
+    before the size) or CORRUPT (a match offset of 0, which the format
+    forbids and the library does not check), and what the oracle wrote is
+    the start of the library's output."""
+    rng = np.random.default_rng([31, len(kind)])
+    data = _data(kind, 60000, rng)
+    codec = pa.Codec("lz4_raw")
+    block = codec.compress(data, asbytes=True)
+    n = len(data)
+    counts = {"same": 0, "both_reject": 0, "oracle_stricter": 0}
+    for _ in range(200):
+        b = bytearray(block)
+        for _ in range(int(rng.integers(1, 4))):
+            b[int(rng.integers(0, len(b)))] = int(rng.integers(0, 256))
+        st, out = _one(bytes(b), n)
+        try:
+            got = codec.decompress(bytes(b), decompressed_size=n, asbytes=True)
+        except Exception:  # the reference library rejected the block
+            assert st != oracle.OK, "the oracle accepts a block the reference library rejects"
+            counts["both_reject"] += 1
+            continue
+        if st == oracle.OK:
+            assert out == got
+            counts["same"] += 1
+        else:
+            assert st in (oracle.E_UNDERFLOW, oracle.E_CORRUPT), st
+            assert out == got[:len(out)]
+            counts["oracle_stricter"] += 1
+    assert counts["same"] > 0 and counts["both_reject"] > 0
